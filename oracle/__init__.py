@@ -1,0 +1,232 @@
+"""CPU FP64 oracle of the explicit M1 radiative-transfer step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check of the
+package entry point and the CPU-baseline leg of the benchmark may import
+this package.  It shares no code with the HIP library (paper_1304_7126_amd):
+the C part (rt_oracle.c) is compiled with gcc, the host physics
+(physics.py) uses numpy/scipy.  Inputs come from rt_inputs only.
+
+The oracle follows the paper (Rosdahl et al. 2013) step by step:
+injection (Sec. 3.1), unsplit GLF/HLL transport with the M1 closure at the
+reduced light speed (Sec. 2, 3.2, 4.1), the subcycled thermochemistry of
+App. A with the rates of App. E.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import physics
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from .build import build
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.or_transport.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp]
+        L.or_inject.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_int, ip, dp, dp]
+        L.or_thermochem.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp,
+                                    dp, dp, ip, ip]
+        L.or_thermochem.restype = ctypes.c_uint
+        L.or_thermo_cell.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_double,
+                                     dp, dp, dp, dp, ip, ip]
+        L.or_thermo_cell.restype = ctypes.c_uint
+        L.or_rate.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
+        L.or_rate.restype = ctypes.c_int
+        L.or_eddington.argtypes = [ctypes.c_double, dp, ctypes.c_double, dp]
+        L.or_face_flux.argtypes = [ctypes.POINTER(OrParams), ctypes.c_int, dp, dp, dp]
+        L.or_courant_dt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.or_courant_dt.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+class OrParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dx", ctypes.c_double),
+        ("bc", ctypes.c_int * 6),
+        ("M", ctypes.c_int),
+        ("c_r", ctypes.c_double),
+        ("sigN", (ctypes.c_double * 3) * 3),
+        ("sigE", (ctypes.c_double * 3) * 3),
+        ("ebar", ctypes.c_double * 3),
+        ("flux", ctypes.c_int),
+        ("otsa", ctypes.c_int),
+        ("isothermal", ctypes.c_int),
+        ("X", ctypes.c_double), ("Y", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("a_exp", ctypes.c_double),
+        ("x_min", ctypes.c_double),
+        ("N_floor", ctypes.c_double),
+        ("max_attempts", ctypes.c_longlong),
+        ("hll", ctypes.POINTER(ctypes.c_double)),
+        ("hll_nf", ctypes.c_int), ("hll_nth", ctypes.c_int),
+    ]
+
+
+RATE_NAMES = ["beta_HI", "beta_HeI", "beta_HeII", "alphaA_HII", "alphaA_HeII", "alphaA_HeIII",
+              "alphaB_HII", "alphaB_HeII", "alphaB_HeIII", "zeta_HI", "zeta_HeI", "zeta_HeII",
+              "etaA_HII", "etaA_HeII", "etaA_HeIII", "etaB_HII", "etaB_HeII", "etaB_HeIII",
+              "psi_HI", "psi_HeII", "theta", "varpi", "omega_HeII"]
+
+
+def rate(name: str, T: float, a_exp: float = 1.0):
+    """(value, d/dT) of an App. E rate coefficient."""
+    v = ctypes.c_double()
+    d = ctypes.c_double()
+    rc = lib().or_rate(RATE_NAMES.index(name), float(T), float(a_exp), ctypes.byref(v), ctypes.byref(d))
+    assert rc == 0
+    return v.value, d.value
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+_HLL_CACHE = {}
+
+
+def hll_table(nf=101, nth=101):
+    key = (nf, nth)
+    if key not in _HLL_CACHE:
+        _HLL_CACHE[key] = physics.hll_table(nf, nth)
+    return _HLL_CACHE[key]
+
+
+class OracleRT:
+    """Oracle for one uniform grid.  State dicts hold float64 numpy arrays:
+    N (M,nz,ny,nx), F (M,3,nz,ny,nx), xHII, xHeII, xHeIII, T, nH (nz,ny,nx)."""
+
+    def __init__(self, n, dx, bc, M, c_r, sigN, sigE, ebar, flux=0, otsa=True,
+                 isothermal=False, X=0.76, Y=0.24, gamma=5.0 / 3.0, a_exp=1.0, x_min=1e-6,
+                 N_floor=0.0, max_attempts=100000, hll=None):
+        p = OrParams()
+        p.nx, p.ny, p.nz = (int(v) for v in n)
+        p.dx = float(dx)
+        for i in range(6):
+            p.bc[i] = int(bc[i])
+        p.M = int(M)
+        p.c_r = float(c_r)
+        for i in range(3):
+            for j in range(3):
+                p.sigN[i][j] = float(sigN[i][j])
+                p.sigE[i][j] = float(sigE[i][j])
+            p.ebar[i] = float(ebar[i])
+        p.flux = int(flux)
+        p.otsa = int(bool(otsa))
+        p.isothermal = int(bool(isothermal))
+        p.X, p.Y = float(X), float(Y)
+        p.gamma = float(gamma)
+        p.a_exp = float(a_exp)
+        p.x_min = float(x_min)
+        p.N_floor = float(N_floor)
+        p.max_attempts = int(max_attempts)
+        self._hll = np.ascontiguousarray(hll if hll is not None else hll_table(), dtype=np.float64)
+        p.hll = _dp(self._hll)
+        p.hll_nf, p.hll_nth = self._hll.shape[0], self._hll.shape[1]
+        self.p = p
+        self.n = tuple(int(v) for v in n)
+        self.M = int(M)
+        self.dx = float(dx)
+        self.c_r = float(c_r)
+
+    @classmethod
+    def for_workload(cls, w, **over):
+        sigN, sigE, ebar, frac = physics.spectrum_attributes(w.spectrum)
+        kw = dict(n=w.n, dx=w.dx, bc=w.bc, M=w.spectrum.M, c_r=w.c_r, sigN=sigN, sigE=sigE,
+                  ebar=ebar, flux=w.flux, otsa=w.otsa, isothermal=w.isothermal, X=w.X, Y=w.Y,
+                  gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min)
+        kw.update(over)
+        o = cls(**kw)
+        o.group_frac = frac[: w.spectrum.M].copy()
+        return o
+
+    def courant_dt(self, courant=0.8):
+        return lib().or_courant_dt(self.dx, self.c_r, float(courant))
+
+    def source_rates(self, ndot_total):
+        """Per-group emission rates (K, M) by the group photon fractions."""
+        f = self.group_frac / self.group_frac.sum() if self.M > 1 else np.ones(1)
+        return np.ascontiguousarray(np.outer(np.asarray(ndot_total, np.float64), f))
+
+    # -- steps ------------------------------------------------------------
+    def inject(self, st, dt, ijk, ndot):
+        ijk = np.ascontiguousarray(ijk, dtype=np.int32)
+        ndot = np.ascontiguousarray(ndot, dtype=np.float64)
+        lib().or_inject(ctypes.byref(self.p), float(dt), int(ijk.shape[0]), _ip(ijk), _dp(ndot),
+                        _dp(st["N"]))
+
+    def transport(self, st, dt):
+        Nout = np.empty_like(st["N"])
+        Fout = np.empty_like(st["F"])
+        lib().or_transport(ctypes.byref(self.p), float(dt), _dp(st["N"]), _dp(st["F"]), _dp(Nout),
+                           _dp(Fout))
+        st["N"], st["F"] = Nout, Fout
+
+    def thermochem(self, st, dt, want_counts=False):
+        nacc = natt = None
+        if want_counts:
+            nacc = np.zeros(st["T"].shape, np.int32)
+            natt = np.zeros(st["T"].shape, np.int32)
+        flags = lib().or_thermochem(ctypes.byref(self.p), float(dt), _dp(st["N"]), _dp(st["F"]),
+                                    _dp(st["xHII"]), _dp(st["xHeII"]), _dp(st["xHeIII"]),
+                                    _dp(st["T"]), _dp(st["nH"]),
+                                    _ip(nacc) if nacc is not None else None,
+                                    _ip(natt) if natt is not None else None)
+        if want_counts:
+            return flags, nacc, natt
+        return flags
+
+    def step(self, st, dt, ijk=None, ndot=None, want_counts=False):
+        """Operator-split RT step of Sec. 3: injection, transport, thermochemistry."""
+        if ijk is not None and len(ijk):
+            self.inject(st, dt, ijk, ndot)
+        self.transport(st, dt)
+        return self.thermochem(st, dt, want_counts=want_counts)
+
+    def thermo_cell(self, dt, nH, N, F, x, T):
+        """One cell (arrays of length M / 3M / 3): returns new values and counts."""
+        N = np.array(N, dtype=np.float64)
+        F = np.array(F, dtype=np.float64)
+        xs = np.array(x, dtype=np.float64)
+        Tc = ctypes.c_double(float(T))
+        a = ctypes.c_int()
+        t = ctypes.c_int()
+        fl = lib().or_thermo_cell(ctypes.byref(self.p), float(dt), float(nH), _dp(N), _dp(F), _dp(xs),
+                                  ctypes.byref(Tc), ctypes.byref(a), ctypes.byref(t))
+        return dict(N=N, F=F, x=xs, T=Tc.value, nacc=a.value, natt=t.value, flags=fl)
+
+    def face_flux(self, d, UL, UR):
+        UL = np.ascontiguousarray(UL, np.float64)
+        UR = np.ascontiguousarray(UR, np.float64)
+        out = np.zeros(4)
+        lib().or_face_flux(ctypes.byref(self.p), int(d), _dp(UL), _dp(UR), _dp(out))
+        return out
+
+
+def eddington(N, F, c):
+    F = np.ascontiguousarray(F, np.float64)
+    D = np.zeros(9)
+    lib().or_eddington(float(N), _dp(F), float(c), _dp(D))
+    return D.reshape(3, 3)
+
+
+def copy_state(st):
+    return {k: np.array(v, copy=True) for k, v in st.items()}
