@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit M1 RT step on one MI355X.
+
+Workload: 256^3 cells x 3 photon groups (lognormal H+He gas, mean n_H =
+1e-3 cm^-3, sigma_ln = 1, 200 sources of 1e47-1e49 photons/s, HLL flux,
+c_r = c/100, Courant 0.8), FP32 N/F transport with FP64 thermochemistry.
+Inputs are synthetic and resident in HBM before the timed region.
+
+Prints one JSON line: metric, value (cell-group updates/s over the timed
+steps), the roofline of the dominant kernel measured live with HIP events on
+the library's stream, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--fp64", action="store_true", help="FP64 transport instead of FP32")
+    ap.add_argument("--flux", choices=["hll", "glf"], default="hll")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(M, fp32):
+    """Bytes one RT step must move per cell: read and write N, F of every
+    group once (4 values x 4 or 8 bytes each way) and the gas state x_HII,
+    x_HeII, x_HeIII, T (FP64, read and write), plus n_H (read)."""
+    rb = 4 if fp32 else 8
+    rad = 2 * 4 * rb * M
+    gas = 2 * 4 * 8 + 8
+    return rad, gas
+
+
+def cpu_baseline(seconds, n_full, M):
+    """The oracle on a 64^3 box of the same recipe (same cell size, sources
+    scaled with volume), stepped until ~`seconds` of wall time."""
+    import numpy as np
+
+    import oracle
+    import rt_inputs as ri
+    n = 64
+    w = ri.lognormal_box(n, 13.2 * n / n_full, max(1, round(200 * (n / n_full) ** 3)), steps=1, seed=0)
+    o = oracle.OracleRT.for_workload(w)
+    st = ri.initial_state(w)
+    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
+    ndot = o.source_rates(nd)
+    dt = o.courant_dt()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(st, dt, ijk, ndot)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    cgu = w.ncell * M * steps / el
+    return {"value": cgu, "unit": "cell-group updates/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n}^3 x {M} groups lognormal box (same recipe and cell size), first {steps} RT steps "
+                      f"from the initial state, {el:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import rt_inputs as ri
+    from paper_1304_7126_amd import RTContext
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    fp32 = not args.fp64
+    n = args.n
+    flux = ri.FLUX_HLL if args.flux == "hll" else ri.FLUX_GLF
+    w = ri.lognormal_box(n, 13.2 * n / 256, max(1, round(200 * (n / 256) ** 3)), steps=args.steps, seed=0,
+                         flux=flux)
+    M = w.spectrum.M
+    print(f"# building {n}^3 x {M} workload", file=sys.stderr, flush=True)
+    st = ri.initial_state(w)
+    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
+    ctx = RTContext.for_workload(w, fp32=fp32)
+    ctx.load_state(st)
+    ctx.set_sources(ijk, ctx.source_rates(nd))
+    dt = ctx.courant_dt()
+    del st
+    stream = torch.cuda.current_stream()
+
+    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.step(dt, 1)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+
+    # timed region: the same launches rt_step makes, with HIP events between
+    # them on the library's stream to time each kernel
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        e = ev[k]
+        e[0].record(stream)
+        ctx.inject(dt)
+        e[1].record(stream)
+        ctx.transport(dt)
+        e[2].record(stream)
+        ctx.thermochem(dt)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_inj = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    t_tr = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    t_ch = sum(e[2].elapsed_time(e[3]) for e in ev) / K
+    s = ctx.stats()
+    ms = wall * 1e3 / K
+    cgu = w.ncell * M * K / wall
+
+    rad, gas = algorithmic_bytes(M, fp32)
+    # each kernel's own algorithmic traffic
+    tr_bytes = w.ncell * rad                    # transport: N, F in and out
+    ch_bytes = w.ncell * (rad + gas)            # chemistry: N, F and gas in and out
+    kern = {"transport": (t_tr, tr_bytes), "thermochem": (t_ch, ch_bytes)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    t_dom, b_dom = kern[dom]
+    achieved = b_dom / (t_dom * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "ms_per_launch": {"inject": t_inj, "transport": t_tr, "thermochem": t_ch},
+            "step_algorithmic_GBps": w.ncell * (rad + gas) / (ms * 1e-3) / 1e9,
+            "step_frac": w.ncell * (rad + gas) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    out = {
+        "metric": "RT cell-group updates/s at 256^3 x 3 groups",
+        "value": cgu,
+        "unit": "cell-group updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 transport / f64 chemistry" if fp32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"lognormal {n}^3 x {M} groups, 200 sources, HLL, c_r=c/100",
+                   "grid": [n, n, n], "groups": M, "flux": args.flux, "precision": "mixed" if fp32 else "fp64",
+                   "parallelism": "1 GPU"},
+        "chem": {"substeps_per_cell_step": s["substeps_total"] / (w.ncell * K),
+                 "attempts_per_cell_step": s["attempts_total"] / (w.ncell * K),
+                 "attempts_max": s["attempts_max"], "flags": s["flags"]},
+        "roofline": roof,
+    }
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, n, M)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

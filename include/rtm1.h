@@ -1,0 +1,220 @@
+/*
+ * rtm1.h -- C ABI of the MI355X explicit M1 radiative-transfer step.
+ *
+ * The library advances, on one uniform Cartesian grid, the photon number
+ * densities N_i and fluxes F_i of M <= 3 photon groups together with the
+ * hydrogen/helium ionisation state and temperature of the gas, with the
+ * method of Rosdahl et al. (2013), "RAMSES-RT":
+ *   - injection of point-source photons          (Sec. 3.1, eq. injnum)
+ *   - explicit GLF or HLL transport of (N, F) with the M1 closure at a
+ *     reduced light speed c_r, unsplit in 3D     (Sec. 2; Sec. 3.2, eqs.
+ *                                                   dUdt_sol, hll, glf;
+ *                                                   Sec. 4.1; App. D)
+ *   - per-cell non-equilibrium thermochemistry, subcycled by the 10% rule
+ *                                                  (Sec. 3.3; App. A; App. E)
+ * operator-split in that order over one time step (Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - cgs units.  Radiation: N [cm^-3], F [cm^-2 s^-1].  T [K].
+ *   - Grids are structure-of-arrays with x fastest: cell (ix,iy,iz) has
+ *     linear index i = ix + nx*(iy + ny*iz), ncell = nx*ny*nz.
+ *   - Device pointers are caller-owned (e.g. torch tensors) and must stay
+ *     valid while bound.  The library allocates only its own small tables
+ *     (HLL eigenvalue table, source list, statistics block); it never
+ *     allocates or frees state arrays.
+ *   - All device work is enqueued on the bound HIP stream and is
+ *     asynchronous; only rt_get_stats and rt_free synchronise.
+ *   - Host-side validation failures return a negative rt_status without
+ *     enqueueing anything; rt_last_error() gives the message.  Device-side
+ *     anomalies set bits in rt_stats.flags.
+ *   - A context is not thread-safe.
+ */
+#ifndef RTM1_H
+#define RTM1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_EINVAL = -1,       /* invalid argument                           */
+    RT_EHIP = -2,         /* a HIP runtime call failed                   */
+    RT_ENOMEM = -3,       /* library table allocation failed             */
+    RT_ESTATE = -4,       /* call not valid in the current context state */
+    RT_EUNSUPPORTED = -5  /* option not supported                        */
+} rt_status;
+
+enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW = 1, RT_BC_REFLECT = 2 };
+enum { RT_FLUX_GLF = 0, RT_FLUX_HLL = 1 };
+/* RT_PREC_FP64: N, F stored and transported in FP64.
+ * RT_PREC_FP32_TRANSPORT: N, F stored and transported in FP32; the
+ * thermochemistry always runs in FP64. */
+enum { RT_PREC_FP64 = 0, RT_PREC_FP32_TRANSPORT = 1 };
+
+/* device-side anomaly bits of rt_stats.flags */
+#define RT_FLAG_CAP 1u   /* a cell hit max_attempts before filling dt (left at its last accepted state) */
+#define RT_FLAG_NAN 2u   /* a non-finite value was produced                                            */
+#define RT_FLAG_NNEG 8u  /* a negative photon density after the chemistry                               */
+
+/* Grid: nx, ny, nz >= 1 cells of width dx [cm].  bc[] for the faces
+ * -x,+x,-y,+y,-z,+z: periodic (must be set on both faces of an axis),
+ * outflow (ghost cell copies the boundary cell) or reflect (ghost mirrors
+ * the boundary cell with the normal flux component negated). */
+typedef struct {
+    int nx, ny, nz;
+    double dx;
+    int bc[6];
+} rt_grid;
+
+/* Photon groups (Sec. 2): M in 1..3; reduced light speed c_r [cm/s];
+ * group-averaged cross sections sigN (eq. csn_multi) and energy-weighted
+ * cross sections sigE (eq. cse_multi) [cm^2], indexed [group][HI,HeI,HeII];
+ * mean photon energies ebar (eq. egy_multi) [erg].  Rows >= M are ignored. */
+typedef struct {
+    int M;
+    double c_r;
+    double sigN[3][3];
+    double sigE[3][3];
+    double ebar[3];
+} rt_groups;
+
+/* Method options.
+ *   flux        RT_FLUX_GLF (eq. glf) or RT_FLUX_HLL (eq. hll)
+ *   otsa        on-the-spot approximation (Sec. 3.3.2): case-B rates, no
+ *               recombination photons; only otsa = 1 is supported
+ *   isothermal  hold T fixed in the thermochemistry (no thermal update)
+ *   prec        RT_PREC_FP64 or RT_PREC_FP32_TRANSPORT
+ *   X, Y        hydrogen and helium mass fractions (X > 0, Y >= 0)
+ *   gamma       ratio of specific heats (5/3)
+ *   a_exp       expansion factor in the Compton term (1 for static boxes)
+ *   x_min       floor on x_HII (1e-6 in the paper's tests)
+ *   N_floor     photon densities <= N_floor skip the 10% check (0: only
+ *               empty groups skip it, as written in App. A)
+ *   max_attempts cap on chemistry attempts per cell per step (>= 1) */
+typedef struct {
+    int flux;
+    int otsa;
+    int isothermal;
+    int prec;
+    double X, Y;
+    double gamma;
+    double a_exp;
+    double x_min;
+    double N_floor;
+    long long max_attempts;
+} rt_params;
+
+/* Caller-owned state.
+ *   N[s]  radiation set s (s = 0, 1): M*ncell elements, layout [g][cell]
+ *   F[s]  3*M*ncell elements, layout [g][axis][cell]
+ *         element type: double (RT_PREC_FP64) or float (FP32 transport).
+ *         Transport reads the current set and writes the other (the
+ *         source/destination copies of App. D); rt_current() says which
+ *         set holds the current state.
+ *   xHII, xHeII, xHeIII, T   FP64, ncell each, updated in place
+ *   nH    FP64, ncell, hydrogen number density [cm^-3], read only
+ *   nacc, natt  optional int32 per-cell counters of accepted substeps and
+ *         of attempts in the last thermochemistry pass (NULL: not written)
+ *   scratch  device buffer of at least rt_scratch_bytes() bytes (reduction
+ *         partials); may be NULL only if rt_get_stats is never called */
+typedef struct {
+    void *N[2];
+    void *F[2];
+    double *xHII, *xHeII, *xHeIII, *T;
+    const double *nH;
+    int32_t *nacc, *natt;
+    void *scratch;
+    size_t scratch_bytes;
+} rt_state;
+
+/* Diagnostics of the current state plus counters accumulated since the
+ * last rt_reset_stats (Sec. 3.3.1 subcycling statistics). */
+typedef struct {
+    double photons[3];        /* sum_cells N_g dx^3                                 */
+    double ionised_H;         /* sum_cells x_HII n_H dx^3 (H ions)                  */
+    double max_f;             /* max reduced flux |F|/(c_r N) over cells with N > 0 */
+    double min_N;             /* min N over all groups and cells                    */
+    long long substeps_total; /* accepted chemistry substeps                        */
+    long long attempts_total; /* chemistry attempts (accepted + restarted)          */
+    long long attempts_max;   /* largest per-cell attempt count in one step         */
+    unsigned flags;           /* RT_FLAG_* bits                                     */
+} rt_stats;
+
+typedef struct rt_ctx rt_ctx;
+
+/* Create a context.  Validates the arguments, builds the HLL eigenvalue
+ * table (Sec. 3.2: extreme eigenvalues of the M1 flux Jacobian on 101x101
+ * nodes of reduced flux f in [0,1] and flux angle in [0,pi]) and uploads it.
+ * Returns RT_OK and *out, or an error (then *out = NULL). */
+rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const rt_params *params, rt_ctx **out);
+
+/* Bytes of device scratch the bound state must provide. */
+size_t rt_scratch_bytes(const rt_ctx *ctx);
+
+/* Bind caller memory (no copies).  Sets the current radiation set to 0. */
+rt_status rt_bind(rt_ctx *ctx, const rt_state *state);
+
+/* Enqueue all later work on this hipStream_t (NULL = the null stream). */
+rt_status rt_set_stream(rt_ctx *ctx, void *hip_stream);
+
+/* Which radiation set (0 or 1) holds the current N, F; and set it. */
+int rt_current(const rt_ctx *ctx);
+rt_status rt_set_current(rt_ctx *ctx, int set);
+
+/* Point sources (Sec. 3.1 with f_esc = 1): n sources at host ijk[3*s+0..2]
+ * = (ix,iy,iz), emitting host ndot[s*M + g] photons/s into group g.
+ * Sources in one cell are summed in input order.  n = 0 removes all. */
+rt_status rt_set_sources(rt_ctx *ctx, int n, const int32_t *ijk, const double *ndot);
+
+/* Courant-limited step dt = courant * dx / (3 c_r) (Sec. 4.1, eq.
+ * dt_courant, with the factor 0.8 of the paper's tests). */
+rt_status rt_courant_dt(const rt_ctx *ctx, double courant, double *dt);
+
+/* Injection: N_g(cell) += ndot_g dt / dx^3 in the current set. */
+rt_status rt_inject(rt_ctx *ctx, double dt);
+
+/* Transport (Sec. 3.2) of every group over dt from the current set into the
+ * other set, which then becomes current.  dt must satisfy dt <= dx/(3 c_r). */
+rt_status rt_transport(rt_ctx *ctx, double dt);
+
+/* Thermochemistry (App. A) of every cell over dt on the current set. */
+rt_status rt_thermochem(rt_ctx *ctx, double dt);
+
+/* nsteps full steps: injection, transport, thermochemistry (Sec. 3).
+ * dt <= 0 uses the Courant step with factor 0.8. */
+rt_status rt_step(rt_ctx *ctx, double dt, int nsteps);
+
+/* Diagnostics of the current state and accumulated counters; synchronises
+ * the stream.  Needs a bound scratch buffer. */
+rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
+rt_status rt_reset_stats(rt_ctx *ctx);
+
+/* Photon-group attributes of a blackbody source at temperature T_bb [K]
+ * for M groups bounded by edges_eV[0..M] (edges_eV[M] may be +inf):
+ * sigN, sigE [cm^2] of eqs. (csn_multi), (cse_multi) with the Verner et
+ * al. fits of App. E.4, ebar [erg] of eq. (egy_multi), and frac[g], the
+ * photon-number fraction of group g over [edges_eV[0], edges_eV[M]].
+ * Host computation by quadrature; output arrays are host [3][3], [3], [3]. */
+rt_status rt_group_attributes(double T_bb, int M, const double *edges_eV, double sigN[3][3],
+                              double sigE[3][3], double ebar[3], double frac[3]);
+
+/* The context's HLL table (host copy, nf*nth*2 doubles, layout
+ * [f][theta][lambda_min, lambda_max], c = 1 units, uniform nodes
+ * f = i/(nf-1), theta = pi k/(nth-1)).  The pointer is owned by ctx. */
+rt_status rt_hll_table(const rt_ctx *ctx, const double **table, int *nf, int *nth);
+
+/* Build the same table on the host into caller memory out[nf*nth*2]
+ * (nf, nth >= 2).  Needs no device. */
+rt_status rt_build_hll_table(int nf, int nth, double *out);
+
+const char *rt_last_error(const rt_ctx *ctx);
+void rt_free(rt_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTM1_H */

@@ -49,6 +49,7 @@ def lib():
         L.or_face_flux.argtypes = [ctypes.POINTER(OrParams), ctypes.c_int, dp, dp, dp]
         L.or_courant_dt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_courant_dt.restype = ctypes.c_double
+        L.or_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -90,6 +91,11 @@ def rate(name: str, T: float, a_exp: float = 1.0):
     rc = lib().or_rate(RATE_NAMES.index(name), float(T), float(a_exp), ctypes.byref(v), ctypes.byref(d))
     assert rc == 0
     return v.value, d.value
+
+
+def threads() -> int:
+    """Number of OpenMP threads the oracle runs with."""
+    return int(lib().or_threads())
 
 
 def _dp(a):

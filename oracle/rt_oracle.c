@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Physical constants, cgs (CODATA 2018).  Ionisation energies from the
  * photoionisation-threshold table of App. E.4. */
@@ -713,4 +716,14 @@ unsigned or_thermochem(const or_params *p, double dt, double *N, double *F, doub
 double or_courant_dt(double dx, double c_r, double courant)
 {
     return courant * dx / (3.0 * c_r);
+}
+
+/* threads the oracle's parallel loops use */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -1,0 +1,564 @@
+// rt_api.hip -- the C ABI of include/rtm1.h: validation, library tables
+// (HLL eigenvalues, sources, statistics), and the launch sequence of the
+// operator-split RT step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+#include "rtm1.h"
+
+using namespace rtm1;
+
+struct rt_ctx {
+    KGrid grid;
+    rt_groups groups;
+    rt_params params;
+    KChem kchem;
+    bool fp32 = false;
+    int nf = 101, nth = 101;
+    std::vector<double> hll_host;
+    void *hll_dev = nullptr;
+    rt_state st;
+    bool bound = false;
+    int cur = 0;
+    hipStream_t stream = nullptr;
+    int nsrc = 0;
+    int32_t *src_cell = nullptr;
+    double *src_rate = nullptr;
+    DevStats *dstats = nullptr;
+    RedOut *dred = nullptr;
+    std::string err;
+};
+
+static thread_local std::string g_init_err;
+
+#define RT_FAIL(ctx, code, ...)                                                    \
+    do {                                                                           \
+        char _b[512];                                                              \
+        snprintf(_b, sizeof(_b), __VA_ARGS__);                                     \
+        (ctx)->err = _b;                                                           \
+        return code;                                                               \
+    } while (0)
+
+#define RT_HIP(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t _e = (call);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            RT_FAIL(ctx, RT_EHIP, "%s failed: %s", #call, hipGetErrorString(_e));                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// HLL eigenvalue table (Sec. 3.2).  Extreme eigenvalues of the M1 flux
+// Jacobian dG_x/dU at c = 1, N = 1, F = f (cos t, sin t, 0).  With
+// s = f^2, a(s) = (1-chi)/2 and b(s) = (3chi-1)/(2s) the pressure row is
+// P_xj = a N d_xj + b F_x F_j / N, whose derivatives give the Jacobian in
+// closed form.  The z-flux mode decouples with speed b f cos t; it is also
+// a root of the (E, F_x, F_y) block, whose other two roots follow from the
+// block's trace and principal minors.  The f = 1 row (a beam) is the limit
+// where all speeds equal cos t.
+// ---------------------------------------------------------------------------
+static void hll_speeds_closed_form(double f, double t, double &lmin, double &lmax)
+{
+    const double s = f * f;
+    const double r = std::sqrt(4.0 - 3.0 * s);
+    const double q = 5.0 + 2.0 * r;
+    const double chi = (3.0 + 4.0 * s) / q;
+    const double chis = (4.0 * q + (3.0 + 4.0 * s) * 3.0 / r) / (q * q);
+    const double a = 0.5 * (1.0 - chi);
+    const double ap = -0.5 * chis;
+    const double b = (3.0 / (2.0 + r) + 6.0) / q;
+    const double drds = -1.5 / r;
+    const double bp = drds * (-3.0 * q / ((2.0 + r) * (2.0 + r)) - 2.0 * (3.0 / (2.0 + r) + 6.0)) / (q * q);
+    const double fx = f * std::cos(t), fy = f * std::sin(t);
+    double J[3][3];
+    J[0][0] = 0.0;
+    J[0][1] = 1.0;
+    J[0][2] = 0.0;
+    J[1][0] = a - 2.0 * s * ap + fx * fx * (-b - 2.0 * s * bp);
+    J[1][1] = 2.0 * ap * fx + 2.0 * b * fx + 2.0 * bp * fx * fx * fx;
+    J[1][2] = 2.0 * ap * fy + 2.0 * bp * fx * fx * fy;
+    J[2][0] = fx * fy * (-b - 2.0 * s * bp);
+    J[2][1] = b * fy + 2.0 * bp * fx * fx * fy;
+    J[2][2] = b * fx + 2.0 * bp * fx * fy * fy;
+    const double lz = b * fx;
+    const double S = J[0][0] + J[1][1] + J[2][2] - lz;
+    const double M2 = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) + (J[0][0] * J[2][2] - J[0][2] * J[2][0]) +
+                      (J[1][1] * J[2][2] - J[1][2] * J[2][1]);
+    const double P = M2 - lz * S;
+    double disc = 0.25 * S * S - P;
+    disc = disc > 0.0 ? std::sqrt(disc) : 0.0;
+    const double lm = 0.5 * S - disc, lp = 0.5 * S + disc;
+    lmin = lm < lz ? lm : lz;
+    lmax = lp > lz ? lp : lz;
+}
+
+static void build_hll(int nf, int nth, std::vector<double> &tab)
+{
+    tab.assign((size_t)nf * nth * 2, 0.0);
+    for (int i = 0; i < nf; ++i) {
+        const double f = (double)i / (nf - 1);
+        for (int k = 0; k < nth; ++k) {
+            const double t = M_PI * (double)k / (nth - 1);
+            double lo, hi;
+            if (i == nf - 1) {
+                lo = hi = std::cos(t);
+            } else {
+                hll_speeds_closed_form(f, t, lo, hi);
+            }
+            tab[((size_t)i * nth + k) * 2 + 0] = lo;
+            tab[((size_t)i * nth + k) * 2 + 1] = hi;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Group attributes (Sec. 2, eqs. csn_multi, egy_multi, cse_multi) of a
+// blackbody by composite Gauss-Legendre quadrature in ln(energy), panels
+// split at the ionisation thresholds; the open last group is cut where the
+// Planck factor has fallen by e^-200.
+// ---------------------------------------------------------------------------
+static const double EPS_ION[3] = {13.60, 24.59, 54.42};
+// Verner et al. (1996) parameters of App. E.4 (HeI eps0 = 13.61 eV)
+static const double VER[3][7] = {{0.4298, 5.475e-14, 2.963, 32.88, 0.0, 0.0, 0.0},
+                                 {13.61, 9.492e-16, 3.188, 1.469, 2.039, 0.4434, 2.136},
+                                 {1.720, 1.369e-14, 2.963, 32.88, 0.0, 0.0, 0.0}};
+
+static double verner(double e, int j)
+{
+    if (e < EPS_ION[j]) return 0.0;
+    const double *p = VER[j];
+    const double x = e / p[0] - p[5];
+    const double y = std::sqrt(x * x + p[6] * p[6]);
+    return p[1] * ((x - 1.0) * (x - 1.0) + p[4] * p[4]) * std::pow(y, 0.5 * p[2] - 5.5) *
+           std::pow(1.0 + std::sqrt(y / p[3]), -p[2]);
+}
+
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// integral over [a,b] (eV) of e^k J(e)/e^? ... : returns {photons, energy,
+// sigma_j * photons (3), sigma_j * energy (3)}
+static void bb_moments(double kT, double a, double b, double out[8])
+{
+    for (int q = 0; q < 8; ++q) out[q] = 0.0;
+    std::vector<double> pts;
+    pts.push_back(a);
+    for (double e : EPS_ION)
+        if (e > a && e < b) pts.push_back(e);
+    pts.push_back(b);
+    std::vector<double> gx, gw;
+    gauss_legendre(24, gx, gw);
+    for (size_t s = 0; s + 1 < pts.size(); ++s) {
+        const double la = std::log(pts[s]), lb = std::log(pts[s + 1]);
+        const int npan = 96;
+        for (int p = 0; p < npan; ++p) {
+            const double l0 = la + (lb - la) * p / npan, l1 = la + (lb - la) * (p + 1) / npan;
+            const double hm = 0.5 * (l1 - l0), cm = 0.5 * (l1 + l0);
+            for (size_t k = 0; k < gx.size(); ++k) {
+                const double l = cm + hm * gx[k];
+                const double e = std::exp(l);
+                const double u = e / kT;
+                if (u > 700.0) continue;
+                // J(e) de = e^3/(exp(e/kT)-1) de, de = e dl
+                const double J = e * e * e / std::expm1(u) * e * hm * gw[k];
+                const double Jn = J / e;
+                out[0] += Jn;
+                out[1] += J;
+                for (int j = 0; j < 3; ++j) {
+                    const double sg = verner(e, j);
+                    out[2 + j] += sg * Jn;
+                    out[5 + j] += sg * J;
+                }
+            }
+        }
+    }
+}
+
+extern "C" rt_status rt_group_attributes(double T_bb, int M, const double *edges_eV, double sigN[3][3],
+                                         double sigE[3][3], double ebar[3], double frac[3])
+{
+    if (!(T_bb > 0) || M < 1 || M > 3 || !edges_eV || !sigN || !sigE || !ebar || !frac) return RT_EINVAL;
+    for (int g = 0; g < M; ++g)
+        if (!(edges_eV[g + 1] > edges_eV[g]) || !(edges_eV[g] > 0)) return RT_EINVAL;
+    const double kT = 8.617333262e-5 * T_bb;
+    const double EVE = 1.602176634e-12;
+    for (int g = 0; g < 3; ++g) {
+        ebar[g] = frac[g] = 0.0;
+        for (int j = 0; j < 3; ++j) sigN[g][j] = sigE[g][j] = 0.0;
+    }
+    double mom[3][8];
+    double ntot = 0.0;
+    for (int g = 0; g < M; ++g) {
+        double a = edges_eV[g], b = edges_eV[g + 1];
+        if (!std::isfinite(b) || b > a + 200.0 * kT) b = std::isfinite(b) ? std::fmin(b, a + 200.0 * kT) : a + 200.0 * kT;
+        bb_moments(kT, a, b, mom[g]);
+        ntot += mom[g][0];
+    }
+    for (int g = 0; g < M; ++g) {
+        frac[g] = mom[g][0] / ntot;
+        ebar[g] = mom[g][1] / mom[g][0] * EVE;
+        for (int j = 0; j < 3; ++j) {
+            sigN[g][j] = mom[g][2 + j] / mom[g][0];
+            sigE[g][j] = mom[g][5 + j] / mom[g][1];
+        }
+    }
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+static rt_status validate(const rt_grid *g, const rt_groups *gr, const rt_params *p, std::string &err)
+{
+    char b[256];
+    if (!g || !gr || !p) { err = "null argument"; return RT_EINVAL; }
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) { err = "grid dimensions must be >= 1"; return RT_EINVAL; }
+    if ((double)g->nx * g->ny * g->nz > 2.0e9) { err = "grid too large (> 2e9 cells)"; return RT_EINVAL; }
+    if (!(g->dx > 0) || !std::isfinite(g->dx)) { err = "dx must be positive"; return RT_EINVAL; }
+    for (int f = 0; f < 6; ++f)
+        if (g->bc[f] < 0 || g->bc[f] > 2) { snprintf(b, sizeof b, "bc[%d] invalid", f); err = b; return RT_EINVAL; }
+    for (int d = 0; d < 3; ++d)
+        if ((g->bc[2 * d] == RT_BC_PERIODIC) != (g->bc[2 * d + 1] == RT_BC_PERIODIC)) {
+            snprintf(b, sizeof b, "axis %d: periodic must be set on both faces", d);
+            err = b;
+            return RT_EINVAL;
+        }
+    if (gr->M < 1 || gr->M > 3) { err = "M must be 1..3"; return RT_EINVAL; }
+    if (!(gr->c_r > 0)) { err = "c_r must be positive"; return RT_EINVAL; }
+    for (int i = 0; i < gr->M; ++i) {
+        if (!(gr->ebar[i] >= 0)) { err = "ebar must be >= 0"; return RT_EINVAL; }
+        for (int j = 0; j < 3; ++j)
+            if (!(gr->sigN[i][j] >= 0) || !(gr->sigE[i][j] >= 0)) { err = "cross sections must be >= 0"; return RT_EINVAL; }
+    }
+    if (p->flux != RT_FLUX_GLF && p->flux != RT_FLUX_HLL) { err = "flux must be GLF or HLL"; return RT_EINVAL; }
+    if (p->otsa != 1) { err = "only the on-the-spot approximation (otsa = 1) is supported"; return RT_EUNSUPPORTED; }
+    if (p->prec != RT_PREC_FP64 && p->prec != RT_PREC_FP32_TRANSPORT) { err = "prec invalid"; return RT_EINVAL; }
+    if (!(p->X > 0) || !(p->Y >= 0) || p->X + p->Y > 1.0 + 1e-12) { err = "need X > 0, Y >= 0, X + Y <= 1"; return RT_EINVAL; }
+    if (!(p->gamma > 1)) { err = "gamma must be > 1"; return RT_EINVAL; }
+    if (!(p->a_exp > 0)) { err = "a_exp must be > 0"; return RT_EINVAL; }
+    if (!(p->x_min > 0) || !(p->x_min < 1)) { err = "x_min must be in (0,1)"; return RT_EINVAL; }
+    if (!(p->N_floor >= 0)) { err = "N_floor must be >= 0"; return RT_EINVAL; }
+    if (p->max_attempts < 1) { err = "max_attempts must be >= 1"; return RT_EINVAL; }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const rt_params *params, rt_ctx **out)
+{
+    if (!out) return RT_EINVAL;
+    *out = nullptr;
+    std::string err;
+    rt_status v = validate(grid, groups, params, err);
+    if (v != RT_OK) {
+        g_init_err = err;
+        return v;
+    }
+    rt_ctx *c = new rt_ctx();
+    c->grid.nx = grid->nx;
+    c->grid.ny = grid->ny;
+    c->grid.nz = grid->nz;
+    for (int f = 0; f < 6; ++f) c->grid.bc[f] = grid->bc[f];
+    c->grid.ncell = (size_t)grid->nx * grid->ny * grid->nz;
+    c->grid.dx = grid->dx;
+    c->groups = *groups;
+    c->params = *params;
+    c->fp32 = params->prec == RT_PREC_FP32_TRANSPORT;
+    KChem &k = c->kchem;
+    k.M = groups->M;
+    k.isothermal = params->isothermal ? 1 : 0;
+    k.cr = groups->c_r;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            k.sN[i][j] = i < groups->M ? groups->sigN[i][j] : 0.0;
+            k.sE[i][j] = i < groups->M ? groups->sigE[i][j] : 0.0;
+        }
+        k.eb[i] = i < groups->M ? groups->ebar[i] : 0.0;
+    }
+    k.X = params->X;
+    k.Y = params->Y;
+    k.Kfac = (params->gamma - 1.0) * params->X / 1.380649e-16;
+    k.a_exp = params->a_exp;
+    k.x_min = params->x_min;
+    k.N_floor = params->N_floor;
+    k.max_att = params->max_attempts;
+
+    build_hll(c->nf, c->nth, c->hll_host);
+    hipError_t e;
+    const size_t ntab = c->hll_host.size();
+    if (c->fp32) {
+        std::vector<float> tf(ntab);
+        for (size_t i = 0; i < ntab; ++i) tf[i] = (float)c->hll_host[i];
+        e = hipMalloc(&c->hll_dev, ntab * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpy(c->hll_dev, tf.data(), ntab * sizeof(float), hipMemcpyHostToDevice);
+    } else {
+        e = hipMalloc(&c->hll_dev, ntab * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMemcpy(c->hll_dev, c->hll_host.data(), ntab * sizeof(double), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&c->dstats, sizeof(DevStats));
+    if (e == hipSuccess) e = hipMemset(c->dstats, 0, sizeof(DevStats));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->dred, sizeof(RedOut));
+    if (e != hipSuccess) {
+        g_init_err = std::string("device table allocation failed: ") + hipGetErrorString(e);
+        rt_free(c);
+        return RT_ENOMEM;
+    }
+    memset(&c->st, 0, sizeof(c->st));
+    *out = c;
+    return RT_OK;
+}
+
+extern "C" size_t rt_scratch_bytes(const rt_ctx *c)
+{
+    (void)c;
+    return reduction_scratch_bytes();
+}
+
+extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
+{
+    if (!c) return RT_EINVAL;
+    if (!s) RT_FAIL(c, RT_EINVAL, "null state");
+    if (!s->N[0] || !s->N[1] || !s->F[0] || !s->F[1]) RT_FAIL(c, RT_EINVAL, "radiation buffers must be non-null");
+    if (s->N[0] == s->N[1] || s->F[0] == s->F[1]) RT_FAIL(c, RT_EINVAL, "the two radiation sets must differ");
+    if (!s->xHII || !s->xHeII || !s->xHeIII || !s->T || !s->nH) RT_FAIL(c, RT_EINVAL, "gas arrays must be non-null");
+    if (s->scratch && s->scratch_bytes < rt_scratch_bytes(c)) RT_FAIL(c, RT_EINVAL, "scratch too small");
+    c->st = *s;
+    c->bound = true;
+    c->cur = 0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_stream(rt_ctx *c, void *stream)
+{
+    if (!c) return RT_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return RT_OK;
+}
+
+extern "C" int rt_current(const rt_ctx *c) { return c ? c->cur : -1; }
+
+extern "C" rt_status rt_set_current(rt_ctx *c, int set)
+{
+    if (!c) return RT_EINVAL;
+    if (set != 0 && set != 1) RT_FAIL(c, RT_EINVAL, "set must be 0 or 1");
+    c->cur = set;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const double *ndot)
+{
+    if (!c) return RT_EINVAL;
+    if (n < 0) RT_FAIL(c, RT_EINVAL, "n < 0");
+    if (n > 0 && (!ijk || !ndot)) RT_FAIL(c, RT_EINVAL, "null source arrays");
+    const int M = c->groups.M;
+    // merge sources per cell, in input order
+    std::vector<int32_t> cells;
+    std::vector<double> rates;
+    for (int s = 0; s < n; ++s) {
+        const int ix = ijk[3 * s], iy = ijk[3 * s + 1], iz = ijk[3 * s + 2];
+        if (ix < 0 || ix >= c->grid.nx || iy < 0 || iy >= c->grid.ny || iz < 0 || iz >= c->grid.nz)
+            RT_FAIL(c, RT_EINVAL, "source %d outside the grid", s);
+        for (int g = 0; g < M; ++g)
+            if (!(ndot[(size_t)s * M + g] >= 0) || !std::isfinite(ndot[(size_t)s * M + g]))
+                RT_FAIL(c, RT_EINVAL, "source %d: rates must be finite and >= 0", s);
+        const int32_t cell = (int32_t)((size_t)ix + (size_t)c->grid.nx * ((size_t)iy + (size_t)c->grid.ny * iz));
+        size_t pos = cells.size();
+        for (size_t q = 0; q < cells.size(); ++q)
+            if (cells[q] == cell) { pos = q; break; }
+        if (pos == cells.size()) {
+            cells.push_back(cell);
+            for (int g = 0; g < M; ++g) rates.push_back(ndot[(size_t)s * M + g]);
+        } else {
+            for (int g = 0; g < M; ++g) rates[pos * M + g] += ndot[(size_t)s * M + g];
+        }
+    }
+    if (c->src_cell) { (void)hipFree(c->src_cell); c->src_cell = nullptr; }
+    if (c->src_rate) { (void)hipFree(c->src_rate); c->src_rate = nullptr; }
+    c->nsrc = 0;
+    if (cells.empty()) return RT_OK;
+    RT_HIP(c, hipMalloc((void **)&c->src_cell, cells.size() * sizeof(int32_t)));
+    RT_HIP(c, hipMalloc((void **)&c->src_rate, rates.size() * sizeof(double)));
+    RT_HIP(c, hipMemcpy(c->src_cell, cells.data(), cells.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    RT_HIP(c, hipMemcpy(c->src_rate, rates.data(), rates.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->nsrc = (int)cells.size();
+    return RT_OK;
+}
+
+extern "C" rt_status rt_courant_dt(const rt_ctx *c, double courant, double *dt)
+{
+    if (!c || !dt || !(courant > 0)) return RT_EINVAL;
+    *dt = courant * c->grid.dx / (3.0 * c->groups.c_r);
+    return RT_OK;
+}
+
+static rt_status check_ready(rt_ctx *c, double dt)
+{
+    if (!c->bound) RT_FAIL(c, RT_ESTATE, "no state bound");
+    if (!(dt > 0) || !std::isfinite(dt)) RT_FAIL(c, RT_EINVAL, "dt must be positive and finite");
+    return RT_OK;
+}
+
+static rt_status do_inject(rt_ctx *c, double dt)
+{
+    const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+    RT_HIP(c, launch_inject(c->fp32, c->st.N[c->cur], c->grid.ncell, c->groups.M, c->nsrc, c->src_cell, c->src_rate,
+                            dt / V, c->stream));
+    return RT_OK;
+}
+
+static rt_status do_transport(rt_ctx *c, double dt)
+{
+    const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
+    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    const int s = c->cur, d = 1 - c->cur;
+    RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, c->groups.c_r, dt, c->st.N[s], c->st.F[s],
+                               c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth, c->stream));
+    c->cur = d;
+    return RT_OK;
+}
+
+static rt_status do_chem(rt_ctx *c, double dt)
+{
+    RT_HIP(c, launch_chem(c->fp32, c->kchem, c->grid.ncell, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
+                          c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, c->dstats,
+                          c->stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_inject(rt_ctx *c, double dt)
+{
+    if (!c) return RT_EINVAL;
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    return do_inject(c, dt);
+}
+
+extern "C" rt_status rt_transport(rt_ctx *c, double dt)
+{
+    if (!c) return RT_EINVAL;
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    return do_transport(c, dt);
+}
+
+extern "C" rt_status rt_thermochem(rt_ctx *c, double dt)
+{
+    if (!c) return RT_EINVAL;
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    return do_chem(c, dt);
+}
+
+extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
+{
+    if (!c) return RT_EINVAL;
+    if (nsteps < 0) RT_FAIL(c, RT_EINVAL, "nsteps < 0");
+    if (!(dt > 0)) dt = 0.8 * c->grid.dx / (3.0 * c->groups.c_r);
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    for (int k = 0; k < nsteps; ++k) {
+        if ((r = do_inject(c, dt)) != RT_OK) return r;
+        if ((r = do_transport(c, dt)) != RT_OK) return r;
+        if ((r = do_chem(c, dt)) != RT_OK) return r;
+    }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_get_stats(rt_ctx *c, rt_stats *out)
+{
+    if (!c || !out) return RT_EINVAL;
+    if (!c->bound) RT_FAIL(c, RT_ESTATE, "no state bound");
+    if (!c->st.scratch) RT_FAIL(c, RT_ESTATE, "rt_get_stats needs a bound scratch buffer");
+    const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+    RT_HIP(c, launch_reduce(c->fp32, c->grid.ncell, c->groups.M, c->groups.c_r, V, c->st.N[c->cur], c->st.F[c->cur],
+                            c->st.xHII, c->st.nH, c->st.scratch, c->dred, c->stream));
+    RedOut r;
+    DevStats d;
+    RT_HIP(c, hipMemcpyAsync(&r, c->dred, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    RT_HIP(c, hipMemcpyAsync(&d, c->dstats, sizeof d, hipMemcpyDeviceToHost, c->stream));
+    RT_HIP(c, hipStreamSynchronize(c->stream));
+    for (int g = 0; g < 3; ++g) out->photons[g] = r.photons[g];
+    out->ionised_H = r.ionised;
+    out->max_f = r.maxf;
+    out->min_N = r.minN;
+    out->substeps_total = (long long)d.acc_total;
+    out->attempts_total = (long long)d.att_total;
+    out->attempts_max = (long long)d.att_max;
+    out->flags = d.flags;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_reset_stats(rt_ctx *c)
+{
+    if (!c) return RT_EINVAL;
+    RT_HIP(c, hipMemsetAsync(c->dstats, 0, sizeof(DevStats), c->stream));
+    return RT_OK;
+}
+
+extern "C" rt_status rt_hll_table(const rt_ctx *c, const double **table, int *nf, int *nth)
+{
+    if (!c || !table || !nf || !nth) return RT_EINVAL;
+    *table = c->hll_host.data();
+    *nf = c->nf;
+    *nth = c->nth;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_build_hll_table(int nf, int nth, double *out)
+{
+    if (nf < 2 || nth < 2 || !out) return RT_EINVAL;
+    std::vector<double> t;
+    build_hll(nf, nth, t);
+    memcpy(out, t.data(), t.size() * sizeof(double));
+    return RT_OK;
+}
+
+extern "C" const char *rt_last_error(const rt_ctx *c)
+{
+    if (!c) return g_init_err.c_str();
+    return c->err.c_str();
+}
+
+extern "C" void rt_free(rt_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    if (c->hll_dev) (void)hipFree(c->hll_dev);
+    if (c->src_cell) (void)hipFree(c->src_cell);
+    if (c->src_rate) (void)hipFree(c->src_rate);
+    if (c->dstats) (void)hipFree(c->dstats);
+    if (c->dred) (void)hipFree(c->dred);
+    delete c;
+}

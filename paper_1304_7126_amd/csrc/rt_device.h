@@ -1,0 +1,242 @@
+// rt_device.h -- device-side physics of the M1 RT step for gfx950.
+//
+// Closure (Sec. 2, eqs. edd2/eddTens/Udir), intercell fluxes (Sec. 3.2,
+// eqs. glf/hll) and the App. E rate coefficients with their T-derivatives.
+// Rates are evaluated from one log(T), sqrt(T) and 1/T per temperature:
+// powers become exp(p ln lambda), the Hui & Gnedin denominators
+// exp(-r log1p((lambda/l0)^q)), and derivatives come from logarithmic
+// derivatives (dv/dT = v/T * dln v/dln T).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtm1 {
+
+constexpr double KB = 1.380649e-16;     // erg/K
+constexpr double EVERG = 1.602176634e-12;
+constexpr double EPS_HI = 13.60 * EVERG;  // App. E.4 threshold table
+constexpr double EPS_HEI = 24.59 * EVERG;
+constexpr double EPS_HEII = 54.42 * EVERG;
+
+// ---------------------------------------------------------------------
+// M1 pressure flux.  For a cell state U = (N, F) the physical flux along
+// axis d is G_d = (F_d, c^2 P_d.), P = N D with
+//   D = (1-chi)/2 I + (3chi-1)/2 n (x) n,  chi = (3+4f^2)/(5+2 sqrt(4-3f^2)),
+//   f = |F|/(c N) capped at 1, n = F/|F|.
+// Written without dividing by |F|: with s = f^2 and r = sqrt(4-3s),
+//   (3chi-1)/(2s) = (3/(2+r) + 6)/(5+2r)  (smooth at s = 0), and
+//   c^2 N (3chi-1)/2 n_d n_k = bb(s) * w * F_d F_k,  w = min(1/N, c^2 N/|F|^2).
+// Outputs the 6 independent components of c^2 P: xx, yy, zz, xy, xz, yz.
+// ---------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6])
+{
+    if (!(N > R(0))) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) P[k] = R(0);
+        return;
+    }
+    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const R cN = c * N;
+    const R cN2 = cN * cN;
+    R s, w;
+    if (F2 > cN2) {
+        s = R(1);
+        w = c * cN / F2;          // c^2 N / |F|^2
+    } else {
+        s = F2 / cN2;
+        w = R(1) / N;
+    }
+    const R r = sqrt(R(4) - R(3) * s);
+    const R inv = R(1) / (R(5) + R(2) * r);
+    const R chi = (R(3) + R(4) * s) * inv;
+    const R iso = R(0.5) * (R(1) - chi) * c * cN;        // c^2 N (1-chi)/2
+    const R bb = (R(3) / (R(2) + r) + R(6)) * inv * w;
+    P[0] = iso + bb * Fx * Fx;
+    P[1] = iso + bb * Fy * Fy;
+    P[2] = iso + bb * Fz * Fz;
+    P[3] = bb * Fx * Fy;
+    P[4] = bb * Fx * Fz;
+    P[5] = bb * Fy * Fz;
+}
+
+// components (c^2 P_dx, c^2 P_dy, c^2 P_dz) of row d
+template <typename R>
+__device__ __forceinline__ void prow(const R P[6], int d, R &px, R &py, R &pz)
+{
+    if (d == 0) { px = P[0]; py = P[3]; pz = P[4]; }
+    else if (d == 1) { px = P[3]; py = P[1]; pz = P[5]; }
+    else { px = P[4]; py = P[5]; pz = P[2]; }
+}
+
+// ---------------------------------------------------------------------
+// HLL wave speeds of a cell along axis d (units of c): bilinear in the
+// table of (lambda_min, lambda_max) over f in [0,1] (nf nodes) and the flux
+// angle theta in [0,pi] (nth nodes), theta = acos(F_d/|F|).
+// ---------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, int nth, R N, R Fx, R Fy,
+                                           R Fz, R Fd, R c, R &lmin, R &lmax)
+{
+    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    const R Fn = sqrt(F2);
+    R f;
+    if (N > R(0)) f = Fn / (c * N);
+    else f = (Fn > R(0)) ? R(1) : R(0);
+    f = f > R(1) ? R(1) : f;
+    R ct = (Fn > R(0)) ? Fd / Fn : R(1);
+    ct = ct > R(1) ? R(1) : (ct < R(-1) ? R(-1) : ct);
+    const R th = acos(ct);
+    const R uf = f * R(nf - 1);
+    const R ut = th * R(0.31830988618379067154) * R(nth - 1);
+    int i = (int)floor(uf), k = (int)floor(ut);
+    i = i > nf - 2 ? nf - 2 : (i < 0 ? 0 : i);
+    k = k > nth - 2 ? nth - 2 : (k < 0 ? 0 : k);
+    const R wf = uf - R(i), wt = ut - R(k);
+    const R *t00 = tab + ((size_t)i * nth + k) * 2;
+    const R *t01 = t00 + 2;
+    const R *t10 = t00 + (size_t)nth * 2;
+    const R *t11 = t10 + 2;
+    const R a00 = (R(1) - wf) * (R(1) - wt), a10 = wf * (R(1) - wt), a01 = (R(1) - wf) * wt, a11 = wf * wt;
+    lmin = a00 * t00[0] + a10 * t10[0] + a01 * t01[0] + a11 * t11[0];
+    lmax = a00 * t00[1] + a10 * t10[1] + a01 * t01[1] + a11 * t11[1];
+}
+
+// ---------------------------------------------------------------------
+// App. E rate coefficients (case B: the library runs with the on-the-spot
+// approximation of Sec. 3.3.2).  vd holds value v and derivative d = dv/dT.
+// ---------------------------------------------------------------------
+struct vd {
+    double v, d;
+};
+
+// per-temperature shared quantities
+struct Tq {
+    double T, lnT, invT, s5, g;  // s5 = sqrt(T/1e5), g = 1/(1+s5)
+};
+
+__device__ __forceinline__ Tq make_Tq(double T)
+{
+    Tq q;
+    q.T = T;
+    q.lnT = log(T);
+    q.invT = 1.0 / T;
+    q.s5 = sqrt(T * 1e-5);
+    q.g = 1.0 / (1.0 + q.s5);
+    return q;
+}
+
+// A sqrt(T) (1+sqrt(T/1e5))^-1 exp(-Tj/T)      (E.1 and the zeta of E.3)
+__device__ __forceinline__ vd r_cen(const Tq &q, double A, double Tj)
+{
+    vd o;
+    o.v = A * sqrt(q.T) * q.g * exp(-Tj * q.invT);
+    const double dl = 0.5 - 0.5 * q.s5 * q.g + Tj * q.invT;  // dln v / dln T
+    o.d = o.v * dl * q.invT;
+    return o;
+}
+
+// A lam^p / (1+(lam/l0)^q)^r, lam = TL/T     (E.2 Hui & Gnedin)
+__device__ __forceinline__ vd r_hg(const Tq &q, double A, double lnTL, double p, double lnl0, double qq,
+                                   double r)
+{
+    const double lnlam = lnTL - q.lnT;
+    const double u = exp(qq * (lnlam - lnl0));
+    vd o;
+    o.v = A * exp(p * lnlam - r * log1p(u));
+    const double dlnlam = p - r * qq * u / (1.0 + u);  // dln v / dln lam
+    o.d = -o.v * dlnlam * q.invT;
+    return o;
+}
+
+// B T lam^p / (1+(lam/l0)^q)^r    (E.3 recombination cooling)
+__device__ __forceinline__ vd r_hgc(const Tq &q, double B, double lnTL, double p, double lnl0, double qq,
+                                    double r)
+{
+    const double lnlam = lnTL - q.lnT;
+    const double u = exp(qq * (lnlam - lnl0));
+    vd o;
+    o.v = B * q.T * exp(p * lnlam - r * log1p(u));
+    const double dlnlam = p - r * qq * u / (1.0 + u);
+    o.d = o.v * (1.0 - dlnlam) * q.invT;
+    return o;
+}
+
+// A lam^p
+__device__ __forceinline__ vd r_pw(const Tq &q, double A, double lnTL, double p)
+{
+    vd o;
+    o.v = A * exp(p * (lnTL - q.lnT));
+    o.d = -p * o.v * q.invT;
+    return o;
+}
+
+// ln of the Hui & Gnedin threshold temperatures and break points
+constexpr double LN_TL_HI = 12.662275226919286;    // ln 315614
+constexpr double LN_TL_HEI = 13.254566388120152;   // ln 570670
+constexpr double LN_TL_HEII = 14.049024154019651;  // ln 1263030
+constexpr double LN_2p74 = 1.007957920399979;
+constexpr double LN_2p25 = 0.8109302162163288;
+
+__device__ __forceinline__ vd beta_HI(const Tq &q) { return r_cen(q, 5.85e-11, 157809.1); }
+__device__ __forceinline__ vd beta_HeI(const Tq &q) { return r_cen(q, 2.38e-11, 285335.4); }
+__device__ __forceinline__ vd beta_HeII(const Tq &q) { return r_cen(q, 5.68e-12, 631515.0); }
+
+__device__ __forceinline__ vd alphaB_HII(const Tq &q)
+{
+    return r_hg(q, 2.753e-14, LN_TL_HI, 1.5, LN_2p74, 0.407, 2.242);
+}
+__device__ __forceinline__ vd alphaB_HeII(const Tq &q) { return r_pw(q, 1.26e-14, LN_TL_HEI, 0.75); }
+__device__ __forceinline__ vd alphaB_HeIII(const Tq &q)
+{
+    return r_hg(q, 5.506e-14, LN_TL_HEII, 1.5, LN_2p74, 0.407, 2.242);
+}
+
+// Primordial cooling L of eq. (rate_cooling), case B (OTSA), and dL/dT.
+__device__ __forceinline__ void cooling_B(const Tq &q, double a_exp, double ne, double nHI, double nHII,
+                                          double nHeI, double nHeII, double nHeIII, double &L, double &dL)
+{
+    const double sqT = sqrt(q.T);
+    // collisional ionisation cooling (Cen form), three species
+    const double e1 = exp(-157809.1 * q.invT);
+    const double e2 = exp(-285335.4 * q.invT);
+    const double e3 = exp(-631515.0 * q.invT);
+    const double cbase = sqT * q.g;                              // sqrt(T)/(1+s5)
+    const double cdl = 0.5 - 0.5 * q.s5 * q.g;                   // dln(cbase)/dlnT
+    const double zHI = 1.27e-21 * cbase * e1, zHIl = cdl + 157809.1 * q.invT;
+    const double zHeI = 9.38e-22 * cbase * e2, zHeIl = cdl + 285335.4 * q.invT;
+    const double zHeII = 4.95e-22 * cbase * e3, zHeIIl = cdl + 631515.0 * q.invT;
+    // collisional excitation
+    const double gdl = -0.5 * q.s5 * q.g;
+    const double psHI = 7.5e-19 * q.g * exp(-118348.0 * q.invT), psHIl = gdl + 118348.0 * q.invT;
+    const double psHeII = 5.54e-17 * exp(-0.397 * q.lnT) * q.g * exp(-473638.0 * q.invT);
+    const double psHeIIl = -0.397 + gdl + 473638.0 * q.invT;
+    // recombination cooling, case B
+    const vd eHII = r_hgc(q, 3.435e-30, LN_TL_HI, 1.97, LN_2p25, 0.376, 3.72);
+    const vd aB2 = r_pw(q, 1.26e-14, LN_TL_HEI, 0.75);
+    const double eHeII = KB * q.T * aB2.v, eHeIIl = 1.0 - 0.75;
+    const vd eHeIII = r_hgc(q, 8.0 * 3.435e-30, LN_TL_HEII, 1.97, LN_2p25, 0.376, 3.72);
+    // dielectronic recombination
+    const double ed1 = exp(-470000.0 * q.invT), ed2 = exp(-94000.0 * q.invT);
+    const double om = 1.24e-13 * exp(-1.5 * q.lnT) * ed1 * (1.0 + 0.3 * ed2);
+    const double oml = -1.5 + 470000.0 * q.invT + 0.3 * ed2 * 94000.0 * q.invT / (1.0 + 0.3 * ed2);
+    // bremsstrahlung and Compton
+    const double th = 1.42e-27 * sqT;
+    const double Tg = 2.727 / a_exp;
+    const double Tg2 = Tg * Tg;
+    const double cpk = 1.017e-37 * Tg2 * Tg2;
+    const double cp = cpk * (q.T - Tg);
+
+    const double cHI = ne * nHI, cHeI = ne * nHeI, cHeII = ne * nHeII;
+    const double cHII = ne * nHII, cHeIII = ne * nHeIII;
+    const double brn = ne * (nHII + nHeII + 4.0 * nHeIII);
+    L = (zHI + psHI) * cHI + zHeI * cHeI + (zHeII + psHeII + eHeII + om) * cHeII + eHII.v * cHII +
+        eHeIII.v * cHeIII + th * brn + cp * ne;
+    // d/dT: value * dln/dlnT / T for the log-derivative terms
+    const double dlog = (zHI * zHIl + psHI * psHIl) * cHI + zHeI * zHeIl * cHeI +
+                        (zHeII * zHeIIl + psHeII * psHeIIl + eHeII * eHeIIl + om * oml) * cHeII +
+                        0.5 * th * brn;
+    dL = dlog * q.invT + eHII.d * cHII + eHeIII.d * cHeIII + cpk * ne;
+}
+
+}  // namespace rtm1
