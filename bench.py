@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--flux", choices=["hll", "glf"], default="hll")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--head-attempts", type=int, default=0, help="chemistry attempts per cell in the first pass")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="after the timed region, copy this many MiB device-to-device 3 times "
+                         "(reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -99,6 +103,8 @@ def main():
     ctx.load_state(st)
     ctx.set_sources(ijk, ctx.source_rates(nd))
     dt = ctx.courant_dt()
+    if args.head_attempts > 0:
+        ctx.set_tuning(args.head_attempts, -1)
     del st
     stream = torch.cuda.current_stream()
 
@@ -108,43 +114,37 @@ def main():
     torch.cuda.synchronize()
     ctx.reset_stats()
 
-    # timed region: the same launches rt_step makes, with HIP events between
-    # them on the library's stream to time each kernel
+    # timed region: rt_step, the production path (injection, then transport
+    # fused with the first chemistry pass, then the compacted tail), with
+    # the library's HIP events bracketing each kernel on its stream
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    ctx.set_timing(True)
+    ctx.timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(K):
-        e = ev[k]
-        e[0].record(stream)
-        ctx.inject(dt)
-        e[1].record(stream)
-        ctx.transport(dt)
-        e[2].record(stream)
-        ctx.thermochem(dt)
-        e[3].record(stream)
+    ctx.step(dt, K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    t_inj = sum(e[0].elapsed_time(e[1]) for e in ev) / K
-    t_tr = sum(e[1].elapsed_time(e[2]) for e in ev) / K
-    t_ch = sum(e[2].elapsed_time(e[3]) for e in ev) / K
+    tm = ctx.timing()
+    ctx.set_timing(False)
     s = ctx.stats()
     ms = wall * 1e3 / K
     cgu = w.ncell * M * K / wall
+    per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tm.items()}
 
     rad, gas = algorithmic_bytes(M, fp32)
-    # each kernel's own algorithmic traffic
-    tr_bytes = w.ncell * rad                    # transport: N, F in and out
-    ch_bytes = w.ncell * (rad + gas)            # chemistry: N, F and gas in and out
-    kern = {"transport": (t_tr, tr_bytes), "thermochem": (t_ch, ch_bytes)}
-    dom = max(kern, key=lambda k: kern[k][0])
-    t_dom, b_dom = kern[dom]
-    achieved = b_dom / (t_dom * 1e-3) / 1e9
-    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "ms_per_launch": {"inject": t_inj, "transport": t_tr, "thermochem": t_ch},
-            "step_algorithmic_GBps": w.ncell * (rad + gas) / (ms * 1e-3) / 1e9,
-            "step_frac": w.ncell * (rad + gas) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    step_bytes = w.ncell * (rad + gas)
+    # the fused head kernel reads the source radiation set and the gas state
+    # and writes the destination set and the gas state: the step's
+    # algorithmic traffic; the tail re-touches only the queued cells
+    t_head = per["head"]
+    achieved = step_bytes / (t_head * 1e-3) / 1e9
+    roof = {"kernel": "k_head (transport fused with the first chemistry pass)", "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "bytes_per_launch": step_bytes,
+            "ms_per_launch": {"inject": per["inject"], "head": per["head"], "tail": per["tail"]},
+            "step_algorithmic_GBps": step_bytes / (ms * 1e-3) / 1e9,
+            "step_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out = {
         "metric": "RT cell-group updates/s at 256^3 x 3 groups",
         "value": cgu,
@@ -168,6 +168,15 @@ def main():
     }
     del ctx
     torch.cuda.empty_cache()
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration * (1 << 20)
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": nb, "write": nb, "launches": 3}
+        del a, b
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, n, M)

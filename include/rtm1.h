@@ -119,8 +119,9 @@ typedef struct {
  *   nH    FP64, ncell, hydrogen number density [cm^-3], read only
  *   nacc, natt  optional int32 per-cell counters of accepted substeps and
  *         of attempts in the last thermochemistry pass (NULL: not written)
- *   scratch  device buffer of at least rt_scratch_bytes() bytes (reduction
- *         partials); may be NULL only if rt_get_stats is never called */
+ *   scratch  device buffer of at least rt_scratch_bytes() bytes: reduction
+ *         partials and the queue of cells still subcycling after the first
+ *         chemistry pass.  Required. */
 typedef struct {
     void *N[2];
     void *F[2];
@@ -185,8 +186,17 @@ rt_status rt_transport(rt_ctx *ctx, double dt);
 rt_status rt_thermochem(rt_ctx *ctx, double dt);
 
 /* nsteps full steps: injection, transport, thermochemistry (Sec. 3).
+ * Transport and thermochemistry run fused in one pass over the grid; the
+ * result equals rt_inject, rt_transport, rt_thermochem in sequence.
  * dt <= 0 uses the Courant step with factor 0.8. */
 rt_status rt_step(rt_ctx *ctx, double dt, int nsteps);
+
+/* Launch tuning (results do not depend on it): head_attempts = chemistry
+ * attempts per cell in the first pass before a cell is queued for the
+ * compacted second pass (1..1000000); queue_cap = queue capacity in cells,
+ * at most the capacity rt_scratch_bytes() was sized for (cells that do not
+ * fit finish in the first pass).  Negative values keep the current one. */
+rt_status rt_set_tuning(rt_ctx *ctx, int head_attempts, long long queue_cap);
 
 /* Diagnostics of the current state and accumulated counters; synchronises
  * the stream.  Needs a bound scratch buffer. */
@@ -210,6 +220,18 @@ rt_status rt_hll_table(const rt_ctx *ctx, const double **table, int *nf, int *nt
 /* Build the same table on the host into caller memory out[nf*nth*2]
  * (nf, nth >= 2).  Needs no device. */
 rt_status rt_build_hll_table(int nf, int nth, double *out);
+
+/* Kernel timing with HIP events on the bound stream.  While enabled, every
+ * launch of the step is bracketed by events; rt_get_timing synchronises the
+ * stream and returns the accumulated milliseconds and launch counts per
+ * kernel class, then clears them.  Disabled by default. */
+typedef struct {
+    double ms[5];       /* inject, transport, chemistry head (fused with
+                           transport in rt_step), chemistry tail, other */
+    long long launches[5];
+} rt_timing;
+rt_status rt_set_timing(rt_ctx *ctx, int enabled);
+rt_status rt_get_timing(rt_ctx *ctx, rt_timing *out);
 
 const char *rt_last_error(const rt_ctx *ctx);
 void rt_free(rt_ctx *ctx);

@@ -266,9 +266,15 @@ int or_rate(int id, double T, double a_exp, double *v, double *d)
 
 /* Eddington tensor D (row-major 3x3) of eqs. (eddTens), (Udir) at light
  * speed c.  f is capped at 1; for F = 0 the n (x) n term vanishes. */
+/* |F| without overflow or underflow of the squares */
+static double norm3(const double F[3])
+{
+    return hypot(hypot(F[0], F[1]), F[2]);
+}
+
 void or_eddington(double N, const double F[3], double c, double D[9])
 {
-    double Fn = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+    double Fn = norm3(F);
     double f = 0.0;
     if (N > 0.0)
         f = Fn / (c * N);
@@ -308,7 +314,7 @@ static void flux_G(int d, const double U[4], double c, double G[4])
  * mapped onto uniform nodes. */
 static void hll_eig(const or_params *p, int d, const double U[4], double *lmin, double *lmax)
 {
-    double Fn = sqrt(U[1] * U[1] + U[2] * U[2] + U[3] * U[3]);
+    double Fn = norm3(U + 1);
     double f;
     if (U[0] > 0.0)
         f = Fn / (p->c_r * U[0]);
@@ -522,6 +528,17 @@ unsigned or_thermo_cell(const or_params *p, double dtRT, double nH, double *N, d
     double rem = dtRT, h = dtRT;
     int acc = 0, att = 0;
     unsigned flags = 0;
+    /* a cell with a non-finite input is reported and left as it is */
+    int finite_in = isfinite(*T) && isfinite(x) && isfinite(y2) && isfinite(y3);
+    for (int g = 0; g < M; g++) {
+        finite_in = finite_in && isfinite(N[g]);
+        for (int d = 0; d < 3; d++) finite_in = finite_in && isfinite(F[3 * g + d]);
+    }
+    if (!finite_in) {
+        *nacc = 0;
+        *natt = 0;
+        return OR_FLAG_NAN;
+    }
 
     while (rem > 0.0) {
         if (att >= p->max_attempts) { flags |= OR_FLAG_CAP; break; }

@@ -21,7 +21,7 @@ EXPORTED = [
     "rt_init", "rt_scratch_bytes", "rt_bind", "rt_set_stream", "rt_current", "rt_set_current",
     "rt_set_sources", "rt_courant_dt", "rt_inject", "rt_transport", "rt_thermochem", "rt_step",
     "rt_get_stats", "rt_reset_stats", "rt_group_attributes", "rt_hll_table", "rt_build_hll_table",
-    "rt_last_error", "rt_free",
+    "rt_last_error", "rt_free", "rt_set_tuning", "rt_set_timing", "rt_get_timing",
 ]
 
 
@@ -57,6 +57,12 @@ class RtStats(ctypes.Structure):
                 ("substeps_total", ctypes.c_longlong), ("attempts_total", ctypes.c_longlong),
                 ("attempts_max", ctypes.c_longlong), ("flags", ctypes.c_uint)]
 
+
+class RtTiming(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_longlong * 5)]
+
+
+TIMING_CLASSES = ("inject", "transport", "head", "tail", "other")
 
 _lib = None
 
@@ -96,6 +102,12 @@ def lib():
         f.restype = st
     L.rt_step.argtypes = [vp, ctypes.c_double, ctypes.c_int]
     L.rt_step.restype = st
+    L.rt_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
+    L.rt_set_tuning.restype = st
+    L.rt_set_timing.argtypes = [vp, ctypes.c_int]
+    L.rt_set_timing.restype = st
+    L.rt_get_timing.argtypes = [vp, ctypes.POINTER(RtTiming)]
+    L.rt_get_timing.restype = st
     L.rt_get_stats.argtypes = [vp, ctypes.POINTER(RtStats)]
     L.rt_get_stats.restype = st
     L.rt_reset_stats.argtypes = [vp]

@@ -19,6 +19,7 @@ struct rt_ctx {
     rt_groups groups;
     rt_params params;
     KChem kchem;
+    KChem *dkchem = nullptr;   // device copy read by the chemistry kernels
     bool fp32 = false;
     int nf = 101, nth = 101;
     std::vector<double> hll_host;
@@ -32,8 +33,66 @@ struct rt_ctx {
     double *src_rate = nullptr;
     DevStats *dstats = nullptr;
     RedOut *dred = nullptr;
+    unsigned qcap = 0;               // chemistry queue capacity (cells)
+    unsigned qcap_max = 0;           // capacity the scratch size is computed for
+    int head_attempts = HEAD_ATTEMPTS;
+    // kernel timing
+    bool timing = false;
+    struct Pend {
+        hipEvent_t a, b;
+        int cls;
+    };
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> pool;
+    double t_ms[5] = {0, 0, 0, 0, 0};
+    long long t_n[5] = {0, 0, 0, 0, 0};
     std::string err;
 };
+
+enum { TM_INJECT = 0, TM_TRANSPORT = 1, TM_HEAD = 2, TM_TAIL = 3, TM_OTHER = 4 };
+
+static hipEvent_t ev_take(rt_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void fold_timing(rt_ctx *c)
+{
+    if (c->pend.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &p : c->pend) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->t_ms[p.cls] += ms;
+            c->t_n[p.cls] += 1;
+        }
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pend.clear();
+}
+
+// run f() between two events of class cls when timing is on
+template <class Fn>
+static rt_status timed(rt_ctx *c, int cls, Fn f)
+{
+    if (!c->timing) return f();
+    if (c->pend.size() > 20000) fold_timing(c);
+    hipEvent_t a = ev_take(c), b = ev_take(c);
+    if (!a || !b) return f();
+    (void)hipEventRecord(a, c->stream);
+    rt_status r = f();
+    (void)hipEventRecord(b, c->stream);
+    c->pend.push_back({a, b, cls});
+    return r;
+}
 
 static thread_local std::string g_init_err;
 
@@ -329,20 +388,35 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     if (e == hipSuccess) e = hipMalloc((void **)&c->dstats, sizeof(DevStats));
     if (e == hipSuccess) e = hipMemset(c->dstats, 0, sizeof(DevStats));
     if (e == hipSuccess) e = hipMalloc((void **)&c->dred, sizeof(RedOut));
+    if (e == hipSuccess) e = hipMalloc((void **)&c->dkchem, sizeof(KChem));
+    if (e == hipSuccess) e = hipMemcpy(c->dkchem, &c->kchem, sizeof(KChem), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         g_init_err = std::string("device table allocation failed: ") + hipGetErrorString(e);
         rt_free(c);
         return RT_ENOMEM;
     }
     memset(&c->st, 0, sizeof(c->st));
+    {
+        // queue for the cells still subcycling after the head pass: an
+        // eighth of the grid (cells beyond it finish in the head pass)
+        size_t cap = c->grid.ncell / 8;
+        if (cap < 4096) cap = c->grid.ncell < 4096 ? c->grid.ncell : 4096;
+        c->qcap = (unsigned)cap;
+        c->qcap_max = (unsigned)cap;
+    }
     *out = c;
     return RT_OK;
 }
 
+static size_t scratch_need(const rt_ctx *c)
+{
+    return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max);
+}
+
 extern "C" size_t rt_scratch_bytes(const rt_ctx *c)
 {
-    (void)c;
-    return reduction_scratch_bytes();
+    if (!c) return 0;
+    return scratch_need(c);
 }
 
 extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
@@ -352,7 +426,8 @@ extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
     if (!s->N[0] || !s->N[1] || !s->F[0] || !s->F[1]) RT_FAIL(c, RT_EINVAL, "radiation buffers must be non-null");
     if (s->N[0] == s->N[1] || s->F[0] == s->F[1]) RT_FAIL(c, RT_EINVAL, "the two radiation sets must differ");
     if (!s->xHII || !s->xHeII || !s->xHeIII || !s->T || !s->nH) RT_FAIL(c, RT_EINVAL, "gas arrays must be non-null");
-    if (s->scratch && s->scratch_bytes < rt_scratch_bytes(c)) RT_FAIL(c, RT_EINVAL, "scratch too small");
+    if (!s->scratch || s->scratch_bytes < scratch_need(c))
+        RT_FAIL(c, RT_EINVAL, "scratch must hold rt_scratch_bytes() = %zu bytes", scratch_need(c));
     c->st = *s;
     c->bound = true;
     c->cur = 0;
@@ -415,6 +490,17 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     return RT_OK;
 }
 
+extern "C" rt_status rt_set_tuning(rt_ctx *c, int head_attempts, long long queue_cap)
+{
+    if (!c) return RT_EINVAL;
+    if (head_attempts == 0 || head_attempts > 1000000) RT_FAIL(c, RT_EINVAL, "head_attempts must be 1..1000000");
+    if (queue_cap > (long long)c->qcap_max)
+        RT_FAIL(c, RT_EINVAL, "queue_cap %lld exceeds the scratch capacity %u", queue_cap, c->qcap_max);
+    if (head_attempts > 0) c->head_attempts = head_attempts;
+    if (queue_cap >= 0) c->qcap = (unsigned)queue_cap;
+    return RT_OK;
+}
+
 extern "C" rt_status rt_courant_dt(const rt_ctx *c, double courant, double *dt)
 {
     if (!c || !dt || !(courant > 0)) return RT_EINVAL;
@@ -432,9 +518,12 @@ static rt_status check_ready(rt_ctx *c, double dt)
 static rt_status do_inject(rt_ctx *c, double dt)
 {
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
-    RT_HIP(c, launch_inject(c->fp32, c->st.N[c->cur], c->grid.ncell, c->groups.M, c->nsrc, c->src_cell, c->src_rate,
-                            dt / V, c->stream));
-    return RT_OK;
+    if (c->nsrc == 0) return RT_OK;
+    return timed(c, TM_INJECT, [&]() -> rt_status {
+        RT_HIP(c, launch_inject(c->fp32, c->st.N[c->cur], c->grid.ncell, c->groups.M, c->nsrc, c->src_cell,
+                                c->src_rate, dt / V, c->stream));
+        return RT_OK;
+    });
 }
 
 static rt_status do_transport(rt_ctx *c, double dt)
@@ -442,17 +531,50 @@ static rt_status do_transport(rt_ctx *c, double dt)
     const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
     if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
     const int s = c->cur, d = 1 - c->cur;
-    RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, c->groups.c_r, dt, c->st.N[s], c->st.F[s],
-                               c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth, c->stream));
+    rt_status r = timed(c, TM_TRANSPORT, [&]() -> rt_status {
+        RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, c->groups.c_r, dt, c->st.N[s],
+                                   c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth, c->stream));
+        return RT_OK;
+    });
+    if (r != RT_OK) return r;
     c->cur = d;
     return RT_OK;
 }
 
 static rt_status do_chem(rt_ctx *c, double dt)
 {
-    RT_HIP(c, launch_chem(c->fp32, c->kchem, c->grid.ncell, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
-                          c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, c->dstats,
-                          c->stream));
+    const QueueView q = queue_view(c->st.scratch, c->qcap, c->qcap_max);
+    for (int part = 1; part <= 2; ++part) {
+        rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
+            RT_HIP(c, launch_chem(part, c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
+                                  c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, q,
+                                  c->head_attempts, c->dstats, c->stream));
+            return RT_OK;
+        });
+        if (r != RT_OK) return r;
+    }
+    return RT_OK;
+}
+
+// transport and thermochemistry in one pass over the grid (source set ->
+// destination set), then the queued cells
+static rt_status do_fused(rt_ctx *c, double dt)
+{
+    const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
+    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    const int s = c->cur, d = 1 - c->cur;
+    const QueueView q = queue_view(c->st.scratch, c->qcap, c->qcap_max);
+    for (int part = 1; part <= 2; ++part) {
+        rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
+            RT_HIP(c, launch_step_fused(part, c->fp32, c->params.flux, c->grid, c->kchem, c->dkchem, dt, c->st.N[s], c->st.F[s],
+                                        c->st.N[d], c->st.F[d], c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T,
+                                        c->st.nH, c->st.nacc, c->st.natt, c->hll_dev, c->nf, c->nth, q,
+                                        c->head_attempts, c->dstats, c->stream));
+            return RT_OK;
+        });
+        if (r != RT_OK) return r;
+    }
+    c->cur = d;
     return RT_OK;
 }
 
@@ -489,8 +611,7 @@ extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
     if (r != RT_OK) return r;
     for (int k = 0; k < nsteps; ++k) {
         if ((r = do_inject(c, dt)) != RT_OK) return r;
-        if ((r = do_transport(c, dt)) != RT_OK) return r;
-        if ((r = do_chem(c, dt)) != RT_OK) return r;
+        if ((r = do_fused(c, dt)) != RT_OK) return r;
     }
     return RT_OK;
 }
@@ -499,7 +620,6 @@ extern "C" rt_status rt_get_stats(rt_ctx *c, rt_stats *out)
 {
     if (!c || !out) return RT_EINVAL;
     if (!c->bound) RT_FAIL(c, RT_ESTATE, "no state bound");
-    if (!c->st.scratch) RT_FAIL(c, RT_ESTATE, "rt_get_stats needs a bound scratch buffer");
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
     RT_HIP(c, launch_reduce(c->fp32, c->grid.ncell, c->groups.M, c->groups.c_r, V, c->st.N[c->cur], c->st.F[c->cur],
                             c->st.xHII, c->st.nH, c->st.scratch, c->dred, c->stream));
@@ -544,6 +664,27 @@ extern "C" rt_status rt_build_hll_table(int nf, int nth, double *out)
     return RT_OK;
 }
 
+extern "C" rt_status rt_set_timing(rt_ctx *c, int enabled)
+{
+    if (!c) return RT_EINVAL;
+    if (!enabled) fold_timing(c);
+    c->timing = enabled != 0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_get_timing(rt_ctx *c, rt_timing *out)
+{
+    if (!c || !out) return RT_EINVAL;
+    fold_timing(c);
+    for (int k = 0; k < 5; ++k) {
+        out->ms[k] = c->t_ms[k];
+        out->launches[k] = c->t_n[k];
+        c->t_ms[k] = 0.0;
+        c->t_n[k] = 0;
+    }
+    return RT_OK;
+}
+
 extern "C" const char *rt_last_error(const rt_ctx *c)
 {
     if (!c) return g_init_err.c_str();
@@ -560,5 +701,11 @@ extern "C" void rt_free(rt_ctx *c)
     if (c->src_rate) (void)hipFree(c->src_rate);
     if (c->dstats) (void)hipFree(c->dstats);
     if (c->dred) (void)hipFree(c->dred);
+    if (c->dkchem) (void)hipFree(c->dkchem);
+    for (auto &p : c->pend) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
     delete c;
 }

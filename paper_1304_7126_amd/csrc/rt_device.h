@@ -18,46 +18,51 @@ constexpr double EPS_HI = 13.60 * EVERG;  // App. E.4 threshold table
 constexpr double EPS_HEI = 24.59 * EVERG;
 constexpr double EPS_HEII = 54.42 * EVERG;
 
+// Reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32 transport, IEEE
+// division in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+
 // ---------------------------------------------------------------------
 // M1 pressure flux.  For a cell state U = (N, F) the physical flux along
 // axis d is G_d = (F_d, c^2 P_d.), P = N D with
 //   D = (1-chi)/2 I + (3chi-1)/2 n (x) n,  chi = (3+4f^2)/(5+2 sqrt(4-3f^2)),
 //   f = |F|/(c N) capped at 1, n = F/|F|.
-// Written without dividing by |F|: with s = f^2 and r = sqrt(4-3s),
-//   (3chi-1)/(2s) = (3/(2+r) + 6)/(5+2r)  (smooth at s = 0), and
-//   c^2 N (3chi-1)/2 n_d n_k = bb(s) * w * F_d F_k,  w = min(1/N, c^2 N/|F|^2).
+// Evaluated in the scaled variable a = F/(c N) so that no square of a
+// tiny density underflows (light fronts carry N down to the bottom of the
+// FP32 range): with s = |a|^2 and r = sqrt(4-3s),
+//   (3chi-1)/(2s) = (3/(2+r) + 6)/(5+2r)   (smooth at s = 0), hence
+//   c^2 P = c^2 N [ (1-chi)/2 I + B a (x) a ],  B = (3chi-1)/(2s) for s <= 1
+//   and B = 1/s (chi = 1, n = a/|a|) when the flux exceeds c N.
 // Outputs the 6 independent components of c^2 P: xx, yy, zz, xy, xz, yz.
 // ---------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6])
 {
-    if (!(N > R(0))) {
+    const R cN = c * N;
+    const R icN = rcp(cN);
+    // empty cells (and densities so close to zero that 1/(c N) overflows)
+    // carry no pressure
+    if (!(N > R(0)) || isinf(icN)) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) P[k] = R(0);
         return;
     }
-    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const R cN = c * N;
-    const R cN2 = cN * cN;
-    R s, w;
-    if (F2 > cN2) {
-        s = R(1);
-        w = c * cN / F2;          // c^2 N / |F|^2
-    } else {
-        s = F2 / cN2;
-        w = R(1) / N;
-    }
+    const R ax = Fx * icN, ay = Fy * icN, az = Fz * icN;
+    const R sr = ax * ax + ay * ay + az * az;
+    const R s = sr > R(1) ? R(1) : sr;
     const R r = sqrt(R(4) - R(3) * s);
-    const R inv = R(1) / (R(5) + R(2) * r);
+    const R inv = rcp(R(5) + R(2) * r);
     const R chi = (R(3) + R(4) * s) * inv;
-    const R iso = R(0.5) * (R(1) - chi) * c * cN;        // c^2 N (1-chi)/2
-    const R bb = (R(3) / (R(2) + r) + R(6)) * inv * w;
-    P[0] = iso + bb * Fx * Fx;
-    P[1] = iso + bb * Fy * Fy;
-    P[2] = iso + bb * Fz * Fz;
-    P[3] = bb * Fx * Fy;
-    P[4] = bb * Fx * Fz;
-    P[5] = bb * Fy * Fz;
+    const R c2N = c * cN;
+    const R iso = R(0.5) * (R(1) - chi) * c2N;
+    const R B = (sr > R(1) ? rcp(sr) : (R(3) * rcp(R(2) + r) + R(6)) * inv) * c2N;
+    P[0] = iso + B * ax * ax;
+    P[1] = iso + B * ay * ay;
+    P[2] = iso + B * az * az;
+    P[3] = B * ax * ay;
+    P[4] = B * ax * az;
+    P[5] = B * ay * az;
 }
 
 // components (c^2 P_dx, c^2 P_dy, c^2 P_dz) of row d
@@ -78,13 +83,26 @@ template <typename R>
 __device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, int nth, R N, R Fx, R Fy,
                                            R Fz, R Fd, R c, R &lmin, R &lmax)
 {
-    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const R Fn = sqrt(F2);
-    R f;
-    if (N > R(0)) f = Fn / (c * N);
-    else f = (Fn > R(0)) ? R(1) : R(0);
-    f = f > R(1) ? R(1) : f;
-    R ct = (Fn > R(0)) ? Fd / Fn : R(1);
+    R f, ct;
+    const R icN = rcp(c * N);
+    if (N > R(0) && !isinf(icN)) {
+        const R ax = Fx * icN, ay = Fy * icN, az = Fz * icN;
+        const R an = sqrt(ax * ax + ay * ay + az * az);
+        f = an > R(1) ? R(1) : an;
+        ct = an > R(0) ? (Fd * icN) * rcp(an) : R(1);
+    } else {
+        // empty cell: a beam if it carries any flux, isotropic otherwise
+        const R m = fmax(fabs(Fx), fmax(fabs(Fy), fabs(Fz)));
+        if (m > R(0)) {
+            const R im = rcp(m);
+            const R bx = Fx * im, by = Fy * im, bz = Fz * im;
+            f = R(1);
+            ct = (Fd * im) * rcp(sqrt(bx * bx + by * by + bz * bz));
+        } else {
+            f = R(0);
+            ct = R(1);
+        }
+    }
     ct = ct > R(1) ? R(1) : (ct < R(-1) ? R(-1) : ct);
     const R th = acos(ct);
     const R uf = f * R(nf - 1);
@@ -112,7 +130,7 @@ struct vd {
 
 // per-temperature shared quantities
 struct Tq {
-    double T, lnT, invT, s5, g;  // s5 = sqrt(T/1e5), g = 1/(1+s5)
+    double T, lnT, invT, sqT, s5, g;  // sqT = sqrt(T), s5 = sqrt(T/1e5), g = 1/(1+s5)
 };
 
 __device__ __forceinline__ Tq make_Tq(double T)
@@ -121,7 +139,8 @@ __device__ __forceinline__ Tq make_Tq(double T)
     q.T = T;
     q.lnT = log(T);
     q.invT = 1.0 / T;
-    q.s5 = sqrt(T * 1e-5);
+    q.sqT = sqrt(T);
+    q.s5 = q.sqT * 3.1622776601683795e-3;  // sqrt(1e-5)
     q.g = 1.0 / (1.0 + q.s5);
     return q;
 }
@@ -130,7 +149,7 @@ __device__ __forceinline__ Tq make_Tq(double T)
 __device__ __forceinline__ vd r_cen(const Tq &q, double A, double Tj)
 {
     vd o;
-    o.v = A * sqrt(q.T) * q.g * exp(-Tj * q.invT);
+    o.v = A * q.sqT * q.g * exp(-Tj * q.invT);
     const double dl = 0.5 - 0.5 * q.s5 * q.g + Tj * q.invT;  // dln v / dln T
     o.d = o.v * dl * q.invT;
     return o;
@@ -196,7 +215,7 @@ __device__ __forceinline__ vd alphaB_HeIII(const Tq &q)
 __device__ __forceinline__ void cooling_B(const Tq &q, double a_exp, double ne, double nHI, double nHII,
                                           double nHeI, double nHeII, double nHeIII, double &L, double &dL)
 {
-    const double sqT = sqrt(q.T);
+    const double sqT = q.sqT;
     // collisional ionisation cooling (Cen form), three species
     const double e1 = exp(-157809.1 * q.invT);
     const double e2 = exp(-285335.4 * q.invT);

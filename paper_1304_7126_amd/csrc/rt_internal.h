@@ -58,9 +58,42 @@ hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c
                             const void *Nin, const void *Fin, void *Nout, void *Fout, const void *hll,
                             int nf, int nth, hipStream_t s);
 
-hipError_t launch_chem(bool fp32, const KChem &kc, size_t ncell, double dt, void *N, void *F, double *xHII,
-                       double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc,
-                       int32_t *natt, DevStats *stats, hipStream_t s);
+// queue of cells still subcycling after the head pass (caller scratch)
+struct QueueView {
+    unsigned *count;  // [0] cells queued, [1] (head) cells taken by the tail
+    unsigned *head;
+    int32_t *cell, *acc, *att;
+    double *v;        // 18 planes of `stride` doubles
+    unsigned cap;     // cells the head pass may queue
+    unsigned stride;  // plane length of the layout
+};
+
+template <typename R>
+struct ChemIO {
+    size_t ncell;
+    R *N, *F;  // destination radiation set
+    double *xHII, *xHeII, *xHeIII, *T;
+    const double *nH;
+    int32_t *nacc, *natt;
+};
+
+constexpr int TAIL_BLOCKS = 1024;
+constexpr int HEAD_ATTEMPTS = 3;
+
+// bytes of scratch for a queue of cap cells (after the reduction partials)
+size_t queue_bytes(unsigned cap);
+// cap: cells the kernels may queue; layout_cap: capacity the scratch is laid out for
+QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
+
+// part 1: queue reset + head pass; part 2: tail pass
+hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
+                       double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
+                       const QueueView &q, int K, DevStats *stats, hipStream_t s);
+
+hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, const KChem &kc, const KChem *dk, double dt, const void *Nin,
+                             const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
+                             double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
+                             int nth, const QueueView &q, int K, DevStats *stats, hipStream_t s);
 
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,

@@ -164,6 +164,10 @@ class RTContext:
         f = self.group_frac / self.group_frac.sum() if self.M > 1 else np.ones(1)
         return np.ascontiguousarray(np.outer(np.asarray(ndot_total, np.float64), f))
 
+    def set_tuning(self, head_attempts=-1, queue_cap=-1):
+        """Launch tuning of the chemistry passes (results do not depend on it)."""
+        check(lib().rt_set_tuning(self._h, int(head_attempts), int(queue_cap)), self._h)
+
     def courant_dt(self, courant=0.8):
         v = ctypes.c_double()
         check(lib().rt_courant_dt(self._h, float(courant), ctypes.byref(v)), self._h)
@@ -208,6 +212,15 @@ class RTContext:
         return {"photons": list(s.photons)[: self.M], "ionised_H": s.ionised_H, "max_f": s.max_f,
                 "min_N": s.min_N, "substeps_total": s.substeps_total, "attempts_total": s.attempts_total,
                 "attempts_max": s.attempts_max, "flags": s.flags}
+
+    def set_timing(self, enabled=True):
+        check(lib().rt_set_timing(self._h, int(bool(enabled))), self._h)
+
+    def timing(self):
+        """{kernel class: (total ms, launches)} since the last call (syncs)."""
+        t = capi.RtTiming()
+        check(lib().rt_get_timing(self._h, ctypes.byref(t)), self._h)
+        return {k: (t.ms[i], t.launches[i]) for i, k in enumerate(capi.TIMING_CLASSES)}
 
     def reset_stats(self):
         check(lib().rt_reset_stats(self._h), self._h)

@@ -252,3 +252,115 @@ def test_courant_violation_rejected():
     from paper_1304_7126_amd.capi import RTError
     with pytest.raises(RTError):
         ctx.transport(2 * ctx.courant_dt(1.0))
+
+
+def _lognormal_ctx(fp32, flux=1, n=20, seed=2, steps=3):
+    RTContext = gpu()
+    w = ri.lognormal_box(n, 6.6 * n / 128, 5, steps=steps, seed=seed, flux=flux)
+    st = ri.initial_state(w)
+    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
+    ctx = RTContext.for_workload(w, fp32=fp32, counters=True)
+    ctx.load_state(st)
+    ctx.set_sources(ijk, ctx.source_rates(nd))
+    return ctx, w
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fused_step_equals_split_sequence(fp32):
+    # rt_step fuses transport and chemistry; it must reproduce
+    # rt_inject, rt_transport, rt_thermochem bit for bit
+    a, w = _lognormal_ctx(fp32)
+    b, _ = _lognormal_ctx(fp32)
+    dt = a.courant_dt()
+    for _ in range(w.steps):
+        a.step(dt, 1)
+        b.inject(dt)
+        b.transport(dt)
+        b.thermochem(dt)
+    ga, gb = a.state_numpy(), b.state_numpy()
+    for k in ("N", "F", "xHII", "xHeII", "xHeIII", "T", "nacc", "natt"):
+        assert np.array_equal(ga[k], gb[k]), k
+
+
+@pytest.mark.parametrize("K,cap", [(1, None), (1, 0), (1, 7), (1000, None), (2, 1)])
+def test_chemistry_tuning_does_not_change_results(K, cap):
+    ref, w = _lognormal_ctx(False, steps=4)
+    alt, _ = _lognormal_ctx(False, steps=4)
+    alt.set_tuning(K, -1 if cap is None else cap)
+    dt = ref.courant_dt()
+    ref.step(dt, w.steps)
+    alt.step(dt, w.steps)
+    ga, gb = ref.state_numpy(), alt.state_numpy()
+    for k in ("N", "F", "xHII", "xHeII", "xHeIII", "T", "nacc", "natt"):
+        assert np.array_equal(ga[k], gb[k]), k
+    sa, sb = ref.stats(), alt.stats()
+    for k in ("substeps_total", "attempts_total", "attempts_max", "flags"):
+        assert sa[k] == sb[k], k
+
+
+@pytest.mark.parametrize("fp32,lo,hi", [(True, -44, -28), (False, -300, -280), (False, -170, -150)])
+def test_transport_tiny_densities_stay_finite(fp32, lo, hi):
+    # light fronts leave densities at the bottom of the floating-point
+    # range; the closure must not form 0/0 from underflowed squares
+    rng = np.random.default_rng(40)
+    n = (24, 9, 7)
+    ctx, o = make_pair(n, BCS[0], 2, 1, fp32=fp32)
+    N = 10.0 ** rng.uniform(lo, hi, (2,) + n[::-1])
+    d = rng.normal(size=(2, 3) + n[::-1])
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    F = d * rng.uniform(0.9, 1.0, (2, 1) + n[::-1]) * C_R * N[:, None]
+    if fp32:
+        N = N.astype(np.float32).astype(np.float64)
+        F = F.astype(np.float32).astype(np.float64)
+    st = {"N": N, "F": np.ascontiguousarray(F), **gas(n, rng)}
+    ctx.load_state(st)
+    dt = ctx.courant_dt()
+    ctx.transport(dt)
+    o.transport(st, dt)
+    g = ctx.state_numpy()
+    assert np.all(np.isfinite(g["N"])) and np.all(np.isfinite(g["F"]))
+    assert np.all(np.isfinite(st["N"]))
+    # compare where the oracle's value is a normal number of the format
+    big = st["N"] > (1e-36 if fp32 else 0)
+    r = np.abs(g["N"] - st["N"])[big] / st["N"][big]
+    assert np.max(r) < (1e-3 if fp32 else 1e-10), np.max(r)
+
+
+def test_nonfinite_cell_is_flagged_and_left_alone():
+    rng = np.random.default_rng(41)
+    n = (16, 4, 4)
+    ctx, o = make_pair(n, BCS[0], 1, 0)
+    N, F = random_rad(n, 1, rng)
+    N *= 1e-3
+    F *= 1e-3
+    st = {"N": N, "F": F, **gas(n, rng)}
+    st["N"][0, 1, 2, 3] = np.nan
+    ctx.load_state(st)
+    dt = ctx.courant_dt()
+    ctx.thermochem(dt)
+    fl, nacc, natt = o.thermochem(st, dt, want_counts=True)
+    g = ctx.state_numpy()
+    s = ctx.stats()
+    assert s["flags"] & 2 and fl & 2
+    assert np.isnan(g["N"][0, 1, 2, 3]) and g["natt"][1, 2, 3] == 0
+    ok = np.ones(n[::-1], bool)
+    ok[1, 2, 3] = False
+    st["nacc"], st["natt"] = nacc, natt
+    assert np.array_equal(g["natt"][ok], natt[ok])
+    assert rel_err(g["xHII"][ok], st["xHII"][ok]) < 1e-12
+
+
+def test_transport_subnormal_densities_stay_finite():
+    # FP64 subnormal densities: 1/(c N) may overflow; such cells are
+    # treated as empty (no pressure) and nothing turns into NaN
+    rng = np.random.default_rng(42)
+    n = (24, 9, 7)
+    ctx, o = make_pair(n, BCS[0], 2, 1)
+    N = 10.0 ** rng.uniform(-322, -305, (2,) + n[::-1])
+    F = np.zeros((2, 3) + n[::-1])
+    F[:, 0] = 0.99 * C_R * N
+    ctx.load_state({"N": N, "F": F, **gas(n, rng)})
+    ctx.step(ctx.courant_dt(), 2)
+    g = ctx.state_numpy()
+    assert np.all(np.isfinite(g["N"])) and np.all(np.isfinite(g["F"]))
+    assert (ctx.stats()["flags"] & 2) == 0
