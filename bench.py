@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--head-attempts", type=int, default=0, help="chemistry attempts per cell in the first pass")
+    ap.add_argument("--form", choices=["grid", "batch"], default="grid",
+                    help="grid: the 256^3 x 3 headline; batch: 64 uneven boxes, batched vs one-by-one")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device 3 times "
                          "(reference kernel for HBM byte counters)")
@@ -78,11 +80,69 @@ def cpu_baseline(seconds, n_full, M):
                       f"from the initial state, {el:.1f} s wall"}
 
 
+def bench_batch(args):
+    """The batching form: 64 periodic boxes (sides 16-96, 1-3 groups, uniform
+    densities, 1-8 sources; FP32 transport, FP64 chemistry, GLF), advanced as
+    one autotuned batch (one graph launch per step) and, for comparison, one
+    box at a time through rt_step."""
+    import torch
+
+    import rt_inputs as ri
+    from paper_1304_7126_amd import RTContext, autotune
+    from paper_1304_7126_amd.batch import batch_from_specs
+    specs = ri.batch_boxes(64, seed=0)
+    dx = 6.6 * ri.KPC / 128
+    b, ws, srcs = batch_from_specs(specs, dx, fp32=True)
+    cg = sum(w.ncell * w.spectrum.M for w in ws)
+    dt = b.courant_dt()
+    tune = autotune.tune_batch(b, dt, trial_steps=2, use_cache=False)
+    b.step(dt, args.warmup)
+    b.synchronize()
+    b.reset_stats()
+    t0 = time.perf_counter()
+    b.step(dt, args.steps)
+    b.synchronize()
+    wall_b = time.perf_counter() - t0
+    st = b.stats()
+    del b
+    torch.cuda.empty_cache()
+    ctxs = []
+    for w, (ijk, nd) in zip(ws, srcs):
+        c = RTContext.for_workload(w, fp32=True)
+        c.load_state(ri.initial_state(w))
+        c.set_sources(ijk, c.source_rates(nd))
+        ctxs.append(c)
+    for _ in range(args.warmup):
+        for c in ctxs:
+            c.step(dt, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for c in ctxs:
+            c.step(dt, 1)
+    torch.cuda.synchronize()
+    wall_u = time.perf_counter() - t0
+    out = {"metric": "RT cell-group updates/s, 64 uneven boxes (batching form)",
+           "value": cg * args.steps / wall_b, "unit": "cell-group updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall_b * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 transport / f64 chemistry", "data": "synthetic",
+           "config": {"workload": "64 periodic boxes, sides {16..96}, 1-3 groups, GLF", "cells": sum(w.ncell for w in ws),
+                      "cell_groups": cg, "tuning": tune["config"]},
+           "one_by_one": {"value": cg * args.steps / wall_u, "ms_per_step": wall_u * 1e3 / args.steps},
+           "speedup_vs_one_by_one": wall_u / wall_b,
+           "chem": {"attempts_per_cell_step": st["attempts_total"] / (sum(w.ncell for w in ws) * args.steps),
+                    "flags": st["flags"]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.form == "batch":
+        return bench_batch(args)
     import numpy as np
     import torch
 
@@ -106,7 +166,6 @@ def main():
     if args.head_attempts > 0:
         ctx.set_tuning(args.head_attempts, -1)
     del st
-    stream = torch.cuda.current_stream()
 
     print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
     for _ in range(args.warmup):

@@ -236,6 +236,59 @@ rt_status rt_get_timing(rt_ctx *ctx, rt_timing *out);
 const char *rt_last_error(const rt_ctx *ctx);
 void rt_free(rt_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Batched form: nbox independent grids ("boxes") of any size, each with its
+ * own 1..3 photon groups, advanced together with the same time step.  One
+ * step is the same method as rt_step on every box; it runs as one HIP graph
+ * (injection, a persistent kernel over 64-cell chunks of all boxes doing
+ * transport and the first chemistry attempts, a persistent kernel finishing
+ * the cells still subcycling).  Each box's result equals rt_step on that box
+ * alone, bit for bit.
+ * --------------------------------------------------------------------- */
+typedef struct rt_batch rt_batch;
+
+/* grids[nbox], groups[nbox] (all with the same c_r), params common to all
+ * boxes.  Validation as rt_init.  1 <= nbox <= 65535. */
+rt_status rt_batch_init(int nbox, const rt_grid *grids, const rt_groups *groups, const rt_params *params,
+                        rt_batch **out);
+
+/* Device scratch the batch needs (chunk counter and the queue of cells still
+ * subcycling, sized for an eighth of all cells). */
+size_t rt_batch_scratch_bytes(const rt_batch *b);
+
+/* states[nbox]: caller-owned arrays of every box as for rt_bind (the scratch
+ * fields of states[] are ignored); scratch of rt_batch_scratch_bytes() bytes.
+ * Sets the current radiation set of all boxes to 0. */
+rt_status rt_batch_bind(rt_batch *b, const rt_state *states, void *scratch, size_t scratch_bytes);
+
+/* Stream for all work; graphs are captured on it, so it must not be the
+ * null stream when graphs are enabled (otherwise steps launch eagerly). */
+rt_status rt_batch_set_stream(rt_batch *b, void *hip_stream);
+
+int rt_batch_current(const rt_batch *b);
+rt_status rt_batch_set_current(rt_batch *b, int set);
+
+/* Sources of one box, as rt_set_sources (ndot[s*M_box + g]). */
+rt_status rt_batch_set_sources(rt_batch *b, int box, int n, const int32_t *ijk, const double *ndot);
+
+/* nsteps steps of every box; dt <= 0 uses 0.8 dx_min/(3 c_r).  dt must
+ * satisfy the Courant limit of the finest box. */
+rt_status rt_batch_step(rt_batch *b, double dt, int nsteps);
+
+/* Launch tuning (results do not depend on it; negative keeps the value):
+ * persistent head blocks per compute unit (1..64), chemistry attempts in the
+ * head pass (1..1e6), tail blocks (1..65536), graphs on/off. */
+rt_status rt_batch_set_tuning(rt_batch *b, int head_blocks_per_cu, int head_attempts, int tail_blocks,
+                              int use_graph);
+
+/* Accumulated chemistry counters and flags of all boxes (the photon fields
+ * of rt_stats are zero); synchronises the stream. */
+rt_status rt_batch_get_stats(rt_batch *b, rt_stats *out);
+rt_status rt_batch_reset_stats(rt_batch *b);
+
+const char *rt_batch_last_error(const rt_batch *b);
+void rt_batch_free(rt_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,10 @@ def lib():
         L.or_courant_dt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_courant_dt.restype = ctypes.c_double
         L.or_threads.restype = ctypes.c_int
+        lp = ctypes.POINTER(ctypes.c_longlong)
+        L.or_step_cells.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp, dp, dp,
+                                    ctypes.c_int, lp, dp, dp, dp, dp, ip, ip]
+        L.or_step_cells.restype = ctypes.c_uint
         _lib = L
     return _lib
 
@@ -206,6 +210,22 @@ class OracleRT:
             self.inject(st, dt, ijk, ndot)
         self.transport(st, dt)
         return self.thermochem(st, dt, want_counts=want_counts)
+
+    def step_cells(self, st, dt, cells):
+        """Transport + thermochemistry of the listed cells (linear indices)
+        from an already-injected source state; returns per-cell results."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        n = cells.size
+        M = self.M
+        out = {"N": np.zeros((n, M)), "F": np.zeros((n, M, 3)), "x": np.zeros((n, 3)), "T": np.zeros(n),
+               "nacc": np.zeros(n, np.int32), "natt": np.zeros(n, np.int32)}
+        c64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        arrs = [c64(st[k]) for k in ("N", "F", "xHII", "xHeII", "xHeIII", "T", "nH")]
+        fl = lib().or_step_cells(ctypes.byref(self.p), float(dt), *[_dp(a) for a in arrs], int(n),
+                                 cells.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _dp(out["N"]),
+                                 _dp(out["F"]), _dp(out["x"]), _dp(out["T"]), _ip(out["nacc"]), _ip(out["natt"]))
+        out["flags"] = fl
+        return out
 
     def thermo_cell(self, dt, nH, N, F, x, T):
         """One cell (arrays of length M / 3M / 3): returns new values and counts."""

@@ -729,6 +729,58 @@ unsigned or_thermochem(const or_params *p, double dt, double *N, double *F, doub
     return flags;
 }
 
+/* Transport and thermochemistry of selected cells only (for sampled checks
+ * of large grids): for each listed cell, the transport of every group from
+ * the source arrays (N, F: already injected), then its thermochemistry.
+ * Outputs per listed cell: Nout[c*M+g], Fout[(c*M+g)*3+d], xs[c*3+0..2],
+ * Tout[c], nacc[c], natt[c].  Returns the OR of the chemistry flags. */
+unsigned or_step_cells(const or_params *p, double dt, const double *N, const double *F, const double *xHII,
+                       const double *xHeII, const double *xHeIII, const double *T, const double *nH, int ncells,
+                       const long long *cells, double *Nout, double *Fout, double *xs, double *Tout, int *nacc,
+                       int *natt)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t nc = (size_t)p->nx * p->ny * p->nz;
+    double k = dt / p->dx;
+    unsigned flags = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : flags)
+    for (int c = 0; c < ncells; c++) {
+        long long i = cells[c];
+        int ix = (int)(i % nx);
+        int iy = (int)((i / nx) % ny);
+        int iz = (int)(i / ((long long)nx * ny));
+        double Nc[3], Fc[9], x3[3], Tc;
+        for (int g = 0; g < p->M; g++) {
+            double UC[4], UL[4], UR[4], Pm[4], Pp[4], acc[4] = {0, 0, 0, 0};
+            load_U(N, F, nc, g, (size_t)i, UC);
+            for (int d = 0; d < 3; d++) {
+                neighbour_U(p, N, F, g, ix, iy, iz, d, -1, UL);
+                neighbour_U(p, N, F, g, ix, iy, iz, d, +1, UR);
+                or_face_flux(p, d, UL, UC, Pm);
+                or_face_flux(p, d, UC, UR, Pp);
+                for (int m = 0; m < 4; m++) acc[m] += Pm[m] - Pp[m];
+            }
+            Nc[g] = UC[0] + k * acc[0];
+            for (int d = 0; d < 3; d++) Fc[3 * g + d] = UC[1 + d] + k * acc[1 + d];
+        }
+        x3[0] = xHII[i];
+        x3[1] = xHeII[i];
+        x3[2] = xHeIII[i];
+        Tc = T[i];
+        int a, t;
+        flags |= or_thermo_cell(p, dt, nH[i], Nc, Fc, x3, &Tc, &a, &t);
+        for (int g = 0; g < p->M; g++) {
+            Nout[(size_t)c * p->M + g] = Nc[g];
+            for (int d = 0; d < 3; d++) Fout[((size_t)c * p->M + g) * 3 + d] = Fc[3 * g + d];
+        }
+        for (int q = 0; q < 3; q++) xs[(size_t)c * 3 + q] = x3[q];
+        Tout[c] = Tc;
+        nacc[c] = a;
+        natt[c] = t;
+    }
+    return flags;
+}
+
 /* Courant-limited RT time step, Sec. 4.1 with the Courant factor of the tests */
 double or_courant_dt(double dx, double c_r, double courant)
 {

@@ -22,6 +22,9 @@ EXPORTED = [
     "rt_set_sources", "rt_courant_dt", "rt_inject", "rt_transport", "rt_thermochem", "rt_step",
     "rt_get_stats", "rt_reset_stats", "rt_group_attributes", "rt_hll_table", "rt_build_hll_table",
     "rt_last_error", "rt_free", "rt_set_tuning", "rt_set_timing", "rt_get_timing",
+    "rt_batch_init", "rt_batch_scratch_bytes", "rt_batch_bind", "rt_batch_set_stream", "rt_batch_current",
+    "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
+    "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
 ]
 
 
@@ -123,6 +126,34 @@ def lib():
     L.rt_last_error.restype = ctypes.c_char_p
     L.rt_free.argtypes = [vp]
     L.rt_free.restype = None
+    # batched form
+    L.rt_batch_init.argtypes = [ctypes.c_int, ctypes.POINTER(RtGrid), ctypes.POINTER(RtGroups),
+                                ctypes.POINTER(RtParams), ctypes.POINTER(vp)]
+    L.rt_batch_init.restype = st
+    L.rt_batch_scratch_bytes.argtypes = [vp]
+    L.rt_batch_scratch_bytes.restype = ctypes.c_size_t
+    L.rt_batch_bind.argtypes = [vp, ctypes.POINTER(RtState), vp, ctypes.c_size_t]
+    L.rt_batch_bind.restype = st
+    L.rt_batch_set_stream.argtypes = [vp, vp]
+    L.rt_batch_set_stream.restype = st
+    L.rt_batch_current.argtypes = [vp]
+    L.rt_batch_current.restype = ctypes.c_int
+    L.rt_batch_set_current.argtypes = [vp, ctypes.c_int]
+    L.rt_batch_set_current.restype = st
+    L.rt_batch_set_sources.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), dp]
+    L.rt_batch_set_sources.restype = st
+    L.rt_batch_step.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+    L.rt_batch_step.restype = st
+    L.rt_batch_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.rt_batch_set_tuning.restype = st
+    L.rt_batch_get_stats.argtypes = [vp, ctypes.POINTER(RtStats)]
+    L.rt_batch_get_stats.restype = st
+    L.rt_batch_reset_stats.argtypes = [vp]
+    L.rt_batch_reset_stats.restype = st
+    L.rt_batch_last_error.argtypes = [vp]
+    L.rt_batch_last_error.restype = ctypes.c_char_p
+    L.rt_batch_free.argtypes = [vp]
+    L.rt_batch_free.restype = None
     _lib = L
     return L
 

@@ -12,8 +12,7 @@
 // Radiation arrays are structure-of-arrays, x fastest, one plane of ncell
 // values per group and component, so a wavefront reads 64 consecutive cells
 // of one component with one coalesced access.
-#include "rt_device.h"
-#include "rt_internal.h"
+#include "rt_cell.h"
 
 namespace rtm1 {
 
@@ -44,167 +43,6 @@ hipError_t launch_inject(bool fp32, void *N, size_t ncell, int M, int nsrc, cons
 }
 
 // --------------------------------------------------------------- transport
-template <typename R>
-struct U4 {
-    R n, fx, fy, fz;
-};
-
-template <typename R>
-__device__ __forceinline__ U4<R> load_u(const R *__restrict__ N, const R *__restrict__ F, size_t nc, uint32_t i)
-{
-    U4<R> u;
-    u.n = N[i];
-    u.fx = F[i];
-    u.fy = F[nc + i];
-    u.fz = F[2 * nc + i];
-    return u;
-}
-
-template <typename R>
-__device__ __forceinline__ R comp(const U4<R> &u, int d)
-{
-    return d == 0 ? u.fx : (d == 1 ? u.fy : u.fz);
-}
-
-// The six neighbours of a cell (-x,+x,-y,+y,-z,+z) with the ghost cells
-// of the boundary conditions: periodic wraps, outflow repeats the cell,
-// reflect repeats it with the normal flux component negated (bit d of refl).
-struct Nbr {
-    uint32_t idx[6];
-    unsigned refl;
-};
-
-__device__ __forceinline__ void cell_coords(const KGrid &g, uint32_t i, int &ix, int &iy, int &iz)
-{
-    const uint32_t nxy = (uint32_t)g.nx * (uint32_t)g.ny;
-    iz = (int)(i / nxy);
-    const uint32_t r = i - (uint32_t)iz * nxy;
-    iy = (int)(r / (uint32_t)g.nx);
-    ix = (int)(r - (uint32_t)iy * (uint32_t)g.nx);
-}
-
-__device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, int iy, int iz)
-{
-    Nbr nb;
-    nb.refl = 0;
-    const int c[3] = {ix, iy, iz};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const uint32_t stride[3] = {1u, (uint32_t)g.nx, (uint32_t)g.nx * (uint32_t)g.ny};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        // low side
-        if (c[d] > 0) {
-            nb.idx[2 * d] = i - stride[d];
-        } else if (g.bc[2 * d] == 0) {
-            nb.idx[2 * d] = i + stride[d] * (uint32_t)(n[d] - 1);
-        } else {
-            nb.idx[2 * d] = i;
-            if (g.bc[2 * d] == 2) nb.refl |= 1u << (2 * d);
-        }
-        // high side
-        if (c[d] < n[d] - 1) {
-            nb.idx[2 * d + 1] = i + stride[d];
-        } else if (g.bc[2 * d + 1] == 0) {
-            nb.idx[2 * d + 1] = i - stride[d] * (uint32_t)(n[d] - 1);
-        } else {
-            nb.idx[2 * d + 1] = i;
-            if (g.bc[2 * d + 1] == 2) nb.refl |= 1u << (2 * d + 1);
-        }
-    }
-    return nb;
-}
-
-// physical flux G_d(U) from the pressure components
-template <typename R>
-__device__ __forceinline__ void flux_of(const U4<R> &u, const R P[6], int d, R G[4])
-{
-    R px, py, pz;
-    prow(P, d, px, py, pz);
-    G[0] = comp(u, d);
-    G[1] = px;
-    G[2] = py;
-    G[3] = pz;
-}
-
-// intercell flux between L and R along axis d: eq. (glf) or eq. (hll);
-// for HLL the wave-speed ranges (lLm, lLp), (lRm, lRp) are in units of c
-template <typename R, int FLUX>
-__device__ __forceinline__ void face_flux(const U4<R> &L, const R PL[6], R lLm, R lLp, const U4<R> &Rt,
-                                          const R PR[6], R lRm, R lRp, int d, R c, R Phi[4])
-{
-    R GL[4], GR[4];
-    flux_of(L, PL, d, GL);
-    flux_of(Rt, PR, d, GR);
-    const R uL[4] = {L.n, L.fx, L.fy, L.fz};
-    const R uR[4] = {Rt.n, Rt.fx, Rt.fy, Rt.fz};
-    if (FLUX == 0) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) Phi[m] = R(0.5) * (GL[m] + GR[m]) - R(0.5) * c * (uR[m] - uL[m]);
-        return;
-    }
-    R lp = lLp > lRp ? lLp : lRp;
-    lp = (lp > R(0) ? lp : R(0)) * c;
-    R lm = lLm < lRm ? lLm : lRm;
-    lm = (lm < R(0) ? lm : R(0)) * c;
-    const R den = lp - lm;
-    if (den == R(0)) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) Phi[m] = R(0.5) * (GL[m] + GR[m]);
-        return;
-    }
-    const R iden = rcp(den);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) Phi[m] = (lp * GL[m] - lm * GR[m] + lp * lm * (uR[m] - uL[m])) * iden;
-}
-
-// Transport of one group of one cell: every face flux from the source
-// arrays (N, F of this group),
-//   U' = U + dt/dx * sum_d (Phi_{d,-1/2} - Phi_{d,+1/2})     (eq. dUdt_sol)
-template <typename R, int FLUX>
-__device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_t nc, const R *__restrict__ N,
-                                                const R *__restrict__ F, R c, R kdx, const R *__restrict__ tab,
-                                                int nf, int nth)
-{
-    const U4<R> C = load_u(N, F, nc, i);
-    R PC[6];
-    m1_pressure(C.n, C.fx, C.fy, C.fz, c, PC);
-    R acc[4] = {R(0), R(0), R(0), R(0)};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        U4<R> L = load_u(N, F, nc, nb.idx[2 * d]);
-        U4<R> Rt = load_u(N, F, nc, nb.idx[2 * d + 1]);
-        if (nb.refl & (1u << (2 * d))) {
-            if (d == 0) L.fx = -L.fx;
-            else if (d == 1) L.fy = -L.fy;
-            else L.fz = -L.fz;
-        }
-        if (nb.refl & (1u << (2 * d + 1))) {
-            if (d == 0) Rt.fx = -Rt.fx;
-            else if (d == 1) Rt.fy = -Rt.fy;
-            else Rt.fz = -Rt.fz;
-        }
-        R PL[6], PR[6], Pm[4], Pp[4];
-        m1_pressure(L.n, L.fx, L.fy, L.fz, c, PL);
-        m1_pressure(Rt.n, Rt.fx, Rt.fy, Rt.fz, c, PR);
-        R lLm = 0, lLp = 0, lCm = 0, lCp = 0, lRm = 0, lRp = 0;
-        if (FLUX == 1) {
-            hll_speeds(tab, nf, nth, L.n, L.fx, L.fy, L.fz, comp(L, d), c, lLm, lLp);
-            hll_speeds(tab, nf, nth, C.n, C.fx, C.fy, C.fz, comp(C, d), c, lCm, lCp);
-            hll_speeds(tab, nf, nth, Rt.n, Rt.fx, Rt.fy, Rt.fz, comp(Rt, d), c, lRm, lRp);
-        }
-        face_flux<R, FLUX>(L, PL, lLm, lLp, C, PC, lCm, lCp, d, c, Pm);
-        face_flux<R, FLUX>(C, PC, lCm, lCp, Rt, PR, lRm, lRp, d, c, Pp);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m] += Pm[m] - Pp[m];
-    }
-    U4<R> o;
-    o.n = C.n + kdx * acc[0];
-    o.fx = C.fx + kdx * acc[1];
-    o.fy = C.fy + kdx * acc[2];
-    o.fz = C.fz + kdx * acc[3];
-    return o;
-}
-
 template <typename R, int FLUX>
 __global__ __launch_bounds__(256) void k_transport(KGrid g, int M, R c, R kdx, const R *__restrict__ Nin,
                                                    const R *__restrict__ Fin, R *__restrict__ Nout,
@@ -247,277 +85,6 @@ hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c
 }
 
 // --------------------------------------------------------- thermochemistry
-__device__ __forceinline__ double mu_of(const KChem &k, double x, double y2, double y3)
-{
-    return 1.0 / (k.X * (1.0 + x) + 0.25 * k.Y * (1.0 + y2 + 2.0 * y3));
-}
-
-__device__ __forceinline__ double rel_change(double a, double b) { return fabs(a - b) / b; }
-
-// Thermochemical state of one cell during its subcycling over dt_RT.
-struct CS {
-    double N[3], F[3][3];
-    double x, y2, y3, Tmu;
-    double rem, h;  // time left in dt_RT, length of the next substep
-    int acc, att;   // accepted substeps, attempts
-};
-
-// Returns false (and leaves the cell untouched) when an input is not finite.
-template <int M>
-__device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, CS &s)
-{
-    bool ok = isfinite(T) && isfinite(s.x) && isfinite(s.y2) && isfinite(s.y3);
-#pragma unroll
-    for (int g = 0; g < M; ++g)
-        ok = ok && isfinite(s.N[g]) && isfinite(s.F[g][0]) && isfinite(s.F[g][1]) && isfinite(s.F[g][2]);
-    s.Tmu = T / mu_of(k, s.x, s.y2, s.y3);
-    s.rem = ok ? dt : 0.0;
-    s.h = dt;
-    s.acc = 0;
-    s.att = 0;
-    return ok;
-}
-
-// One attempt of a substep of length h (App. A tasks 1-5).  On a failed
-// 10% check the state is unchanged and h is halved; on success the state
-// advances by h, and the next h doubles when the largest relative change
-// was below 5%.  Returns true when the cell has filled dt_RT (or reached
-// the attempt cap, flag bit 0).
-template <int M>
-__device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double Tiso, CS &s, unsigned &flags)
-{
-    if (s.att >= k.max_att) {
-        flags |= 1u;
-        return true;
-    }
-    ++s.att;
-    const bool iso = k.isothermal != 0;
-    const double nHe = nH * k.Y / (4.0 * k.X);
-    const double K = k.Kfac / nH;
-    double h = s.h;
-    if (h >= s.rem * (1.0 - 1e-10)) h = s.rem;
-    const double x = s.x, y2 = s.y2, y3 = s.y3, Tmu = s.Tmu;
-    double maxrel = 0.0, r;
-    // ---- photons: semi-implicit absorption with backward abundances
-    const double nHI = (1.0 - x) * nH;
-    const double nHeI = (1.0 - y2 - y3) * nHe;
-    const double nHeII = y2 * nHe;
-    const double nHII = x * nH;
-    const double nHeIII = y3 * nHe;
-    double Nn[M], Fn[M][3];
-    bool fail = false;
-#pragma unroll
-    for (int g = 0; g < M; ++g) {
-        const double D = k.cr * (k.sN[g][0] * nHI + k.sN[g][1] * nHeI + k.sN[g][2] * nHeII);
-        const double rden = 1.0 / (1.0 + h * D);
-        Nn[g] = s.N[g] * rden;
-        Fn[g][0] = s.F[g][0] * rden;
-        Fn[g][1] = s.F[g][1] * rden;
-        Fn[g][2] = s.F[g][2] * rden;
-        r = s.N[g] > k.N_floor ? rel_change(Nn[g], s.N[g]) : 0.0;
-        fail |= r > 0.1;
-        maxrel = r > maxrel ? r : maxrel;
-    }
-    if (fail) {
-        s.h = 0.5 * h;
-        return false;
-    }
-    const double mu0 = mu_of(k, x, y2, y3);
-    const double ne0 = nHII + (y2 + 2.0 * y3) * nHe;
-    // ---- thermal update in T_mu = T/mu
-    double Tmun = Tmu;
-    if (!iso) {
-        const Tq q0 = make_Tq(Tmu * mu0);
-        double H = 0.0;
-        {
-            const double nj[3] = {nHI, nHeI, nHeII};
-            const double ej[3] = {EPS_HI, EPS_HEI, EPS_HEII};
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                double sj = 0.0;
-#pragma unroll
-                for (int g = 0; g < M; ++g) sj += k.cr * Nn[g] * (k.eb[g] * k.sE[g][j] - ej[j] * k.sN[g][j]);
-                H += nj[j] * sj;
-            }
-        }
-        double L, dL;
-        cooling_B(q0, k.a_exp, ne0, nHI, nHII, nHeI, nHeII, nHeIII, L, dL);
-        const double Lam = H - L;
-        const double Lamp = -mu0 * dL;
-        const double den = 1.0 - Lamp * K * h;
-        if (!(den > 0.0)) {
-            s.h = 0.5 * h;
-            return false;
-        }
-        Tmun = Tmu + Lam * K * h / den;
-        r = rel_change(Tmun, Tmu);
-        if (r > 0.1 || fabs(K * Lam * h) / Tmu > 0.1) {
-            s.h = 0.5 * h;
-            return false;
-        }
-        maxrel = r > maxrel ? r : maxrel;
-    }
-    // ---- hydrogen: semi-implicit in x_HII
-    double GHI = 0.0, GHeI = 0.0, GHeII = 0.0;
-#pragma unroll
-    for (int g = 0; g < M; ++g) {
-        GHI += k.sN[g][0] * k.cr * Nn[g];
-        GHeI += k.sN[g][1] * k.cr * Nn[g];
-        GHeII += k.sN[g][2] * k.cr * Nn[g];
-    }
-    const Tq q1 = make_Tq(iso ? Tiso : Tmun * mu0);
-    const vd bH = beta_HI(q1);
-    const vd aH = alphaB_HII(q1);
-    const double Cr = bH.v * ne0 + GHI;
-    const double Dr = aH.v * ne0;
-    double dC, dD;
-    if (iso) {
-        dC = nH * bH.v;
-        dD = nH * aH.v;
-    } else {
-        const double f = ne0 * Tmun * mu0 * mu0 * k.X;
-        dC = nH * bH.v - f * bH.d;
-        dD = nH * aH.v - f * aH.d;
-    }
-    const double J = dC - (Cr + Dr) - x * (dC + dD);
-    const double denx = 1.0 - J * h;
-    if (!(denx > 0.0)) {
-        s.h = 0.5 * h;
-        return false;
-    }
-    const double rate = Cr - x * (Cr + Dr);
-    double xn = x + h * rate / denx;
-    xn = xn < k.x_min ? k.x_min : (xn > 1.0 ? 1.0 : xn);
-    r = rel_change(xn, x);
-    if (r > 0.1 || fabs(rate) * h / x > 0.1) {
-        s.h = 0.5 * h;
-        return false;
-    }
-    maxrel = r > maxrel ? r : maxrel;
-    // ---- helium: HeI, HeII, HeIII in order, then He conservation
-    double y2n = y2, y3n = y3;
-    if (nHe > 0.0) {
-        const double ne1 = xn * nH + (y2 + 2.0 * y3) * nHe;
-        const Tq q2 = make_Tq(iso ? Tiso : Tmun * mu_of(k, xn, y2, y3));
-        const vd bHe1 = beta_HeI(q2), aHe2 = alphaB_HeII(q2), bHe2 = beta_HeII(q2), aHe3 = alphaB_HeIII(q2);
-        const double y1 = 1.0 - y2 - y3;
-        const double y1n = (y1 + y2 * aHe2.v * ne1 * h) / (1.0 + (bHe1.v * ne1 + GHeI) * h);
-        y2n = (y2 + (y1n * (bHe1.v * ne1 + GHeI) + y3 * aHe3.v * ne1) * h) /
-              (1.0 + ((bHe2.v + aHe2.v) * ne1 + GHeII) * h);
-        const double ne2 = xn * nH + (y2n + 2.0 * y3) * nHe;
-        const Tq q3 = make_Tq(iso ? Tiso : Tmun * mu_of(k, xn, y2n, y3));
-        const vd bHe2b = beta_HeII(q3), aHe3b = alphaB_HeIII(q3);
-        y3n = (y3 + y2n * (bHe2b.v * ne2 + GHeII) * h) / (1.0 + aHe3b.v * ne2 * h);
-        const double S = y1n + y2n + y3n;
-        if (!(y1n >= y2n && y1n >= y3n)) {
-            if (y2n >= y3n) y2n -= (S - 1.0);
-            else y3n -= (S - 1.0);
-        }
-    }
-    // ---- electron density check
-    const double nen = xn * nH + (y2n + 2.0 * y3n) * nHe;
-    r = rel_change(nen, ne0);
-    if (r > 0.1) {
-        s.h = 0.5 * h;
-        return false;
-    }
-    maxrel = r > maxrel ? r : maxrel;
-    // ---- accept
-#pragma unroll
-    for (int g = 0; g < M; ++g) {
-        s.N[g] = Nn[g];
-        s.F[g][0] = Fn[g][0];
-        s.F[g][1] = Fn[g][1];
-        s.F[g][2] = Fn[g][2];
-    }
-    s.x = xn;
-    s.y2 = y2n;
-    s.y3 = y3n;
-    s.Tmu = iso ? Tiso / mu_of(k, xn, y2n, y3n) : Tmun;
-    s.rem -= h;
-    ++s.acc;
-    s.h = maxrel < 0.05 ? 2.0 * h : h;
-    return !(s.rem > 0.0);
-}
-
-template <int M>
-__device__ __forceinline__ double chem_finish(const KChem &k, double Tiso, const CS &s, unsigned &flags)
-{
-    const double T = k.isothermal ? Tiso : s.Tmu * mu_of(k, s.x, s.y2, s.y3);
-#pragma unroll
-    for (int g = 0; g < M; ++g) {
-        if (s.N[g] < 0.0) flags |= 8u;
-        if (!isfinite(s.N[g])) flags |= 2u;
-    }
-    if (!isfinite(T) || !isfinite(s.x)) flags |= 2u;
-    return T;
-}
-
-// Queue of cells still subcycling after the head pass (structure of arrays
-// in caller scratch): the cell index, the attempt counters, and the partial
-// state {N[3], F[3][3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}.
-constexpr int QV = 18;
-
-__device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t cell, const CS &s)
-{
-    q.cell[p] = (int32_t)cell;
-    q.acc[p] = s.acc;
-    q.att[p] = s.att;
-    double *v = q.v + p;
-    const size_t c = q.stride;
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        v[(size_t)g * c] = s.N[g];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[(size_t)(3 + 3 * g + d) * c] = s.F[g][d];
-    }
-    v[12 * c] = s.x;
-    v[13 * c] = s.y2;
-    v[14 * c] = s.y3;
-    v[15 * c] = s.Tmu;
-    v[16 * c] = s.rem;
-    v[17 * c] = s.h;
-}
-
-__device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, CS &s)
-{
-    s.acc = q.acc[p];
-    s.att = q.att[p];
-    const double *v = q.v + p;
-    const size_t c = q.stride;
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
-        s.N[g] = v[(size_t)g * c];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) s.F[g][d] = v[(size_t)(3 + 3 * g + d) * c];
-    }
-    s.x = v[12 * c];
-    s.y2 = v[13 * c];
-    s.y3 = v[14 * c];
-    s.Tmu = v[15 * c];
-    s.rem = v[16 * c];
-    s.h = v[17 * c];
-    return (uint32_t)q.cell[p];
-}
-
-template <typename R, int M>
-__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const CS &s, double T)
-{
-    const size_t nc = io.ncell;
-#pragma unroll
-    for (int g = 0; g < M; ++g) {
-        io.N[(size_t)g * nc + i] = (R)s.N[g];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) io.F[(size_t)(3 * g + d) * nc + i] = (R)s.F[g][d];
-    }
-    io.xHII[i] = s.x;
-    io.xHeII[i] = s.y2;
-    io.xHeIII[i] = s.y3;
-    io.T[i] = T;
-    if (io.nacc) io.nacc[i] = s.acc;
-    if (io.natt) io.natt[i] = s.att;
-}
-
 // Per-block reduction of the chemistry counters; one atomic per block.
 __device__ __forceinline__ void block_stats(DevStats *st, unsigned long long acc, unsigned long long att,
                                             unsigned long long mx, unsigned fl)
