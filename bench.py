@@ -34,7 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--head-attempts", type=int, default=0, help="chemistry attempts per cell in the first pass")
-    ap.add_argument("--form", choices=["grid", "batch"], default="grid",
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--form", choices=["grid", "batch", "adjoint"], default="grid",
                     help="grid: the 256^3 x 3 headline; batch: 64 uneven boxes, batched vs one-by-one")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device 3 times "
@@ -136,6 +137,58 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def adjoint_cost(steps=300, every=20):
+    """Cost of the gradient of L = sum (x_HII - target)^2 after `steps`
+    steps of the differentiation workload (64^3, one grey group, hydrogen
+    only, 16 sources, FP64) with checkpoints every `every` steps, against
+    the plain forward run (rt_step, no checkpoints) on the same GPU."""
+    import numpy as np
+    import torch
+
+    import rt_inputs as ri
+    from paper_1304_7126_amd import RTContext
+    from paper_1304_7126_amd.adjoint import GradientRun
+
+    w = ri.grey_64(steps=steps)
+    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
+    st = ri.initial_state(w)
+    lnnd = torch.tensor(np.log(nd), dtype=torch.float64)
+    lnnH = torch.tensor(np.log(st["nH"]), dtype=torch.float64, device="cuda")
+    plain = RTContext.for_workload(w)
+    dt = plain.courant_dt()
+    ctx = RTContext.for_workload(w, counters=True)
+    run = GradientRun(ctx, ijk, dt, steps, x0=w.xHII0, T0=w.T0, every=every)
+
+    def t_plain():
+        plain.load_state(st)
+        plain.set_sources(ijk, nd.reshape(-1, 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain.step(dt, steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    target = run.forward(torch.tensor(ri.perturbed_log_rates(nd, w.seed)), lnnH).clone()
+    tp = min(t_plain() for _ in range(3))
+    times = []
+    for _ in range(2):  # the first pass warms the allocator
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = run.forward(lnnd, lnnH)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g_src, g_nH = run.backward(2.0 * (x - target))[:2]
+        torch.cuda.synchronize()
+        times.append((t1 - t0, time.perf_counter() - t1))
+    tf, tb = times[-1]
+    return {"workload": f"grey {w.n[0]}^3 x 1 group, H only, 16 sources, {steps} steps, checkpoints every {every}, "
+                        "GLF, FP64",
+            "forward_ms": tp * 1e3, "forward_checkpointed_ms": tf * 1e3, "backward_ms": tb * 1e3,
+            "ratio": tb / tp, "ratio_with_forward": (tf + tb) / tp,
+            "trace_entries_max": run.last_backward.get("trace_entries_max"),
+            "grad_finite": bool(torch.isfinite(g_src).all().item() and torch.isfinite(g_nH).all().item())}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -143,6 +196,13 @@ def main():
         sys.exit(2)
     if args.form == "batch":
         return bench_batch(args)
+    if args.form == "adjoint":
+        a = adjoint_cost()
+        print(json.dumps({"metric": "adjoint/forward cost ratio", "value": a["ratio"], "unit": "x",
+                          "n_gpus": 1, "steps": 300, "warmup": 1, "ms_per_step": a["backward_ms"] / 300,
+                          "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": a["workload"]}, "adjoint": a}), flush=True)
+        return
     import numpy as np
     import torch
 
@@ -205,7 +265,7 @@ def main():
             "step_algorithmic_GBps": step_bytes / (ms * 1e-3) / 1e9,
             "step_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out = {
-        "metric": "RT cell-group updates/s at 256^3 x 3 groups",
+        "metric": "RT cell-group updates/s at 256^3 x 3 groups; adjoint/forward cost ratio",
         "value": cgu,
         "unit": "cell-group updates/s",
         "n_gpus": 1,
@@ -227,6 +287,10 @@ def main():
     }
     del ctx
     torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        print("# adjoint cost (64^3 differentiation workload)", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_cost()
+        torch.cuda.empty_cache()
     if args.copy_calibration > 0:
         nb = args.copy_calibration * (1 << 20)
         a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")

@@ -59,6 +59,8 @@ enum { RT_PREC_FP64 = 0, RT_PREC_FP32_TRANSPORT = 1 };
 #define RT_FLAG_CAP 1u   /* a cell hit max_attempts before filling dt (left at its last accepted state) */
 #define RT_FLAG_NAN 2u   /* a non-finite value was produced                                            */
 #define RT_FLAG_NNEG 8u  /* a negative photon density after the chemistry                               */
+#define RT_FLAG_TRACE 16u /* rt_step_record: a cell took another number of substeps than tape.counts,
+                             or the trace capacity was too small (the adjoint of that cell is wrong)   */
 
 /* Grid: nx, ny, nz >= 1 cells of width dx [cm].  bc[] for the faces
  * -x,+x,-y,+y,-z,+z: periodic (must be set on both faces of an axis),
@@ -288,6 +290,86 @@ rt_status rt_batch_reset_stats(rt_batch *b);
 
 const char *rt_batch_last_error(const rt_batch *b);
 void rt_batch_free(rt_batch *b);
+
+/* ---------------------------------------------------------------------
+ * Differentiation form: the reverse (adjoint) pass of rt_step, giving
+ * dL/dln Ndot_s for every source and dL/dln n_H for every cell of a scalar
+ * L of the state after some steps.
+ *
+ * Supported configuration (RT_EUNSUPPORTED otherwise): one photon group,
+ * hydrogen-only gas (Y = 0), GLF flux, periodic boundaries on all faces,
+ * RT_PREC_FP64.  Isothermal and temperature-evolving gas are both supported.
+ *
+ * Of step k (U_k -> injection -> U_a -> transport -> U_b -> chemistry ->
+ * U_k+1) the adjoint applies the transposes of
+ *   - the chemistry (App. A): per cell, its accepted substeps in reverse,
+ *     each linearised at the state recorded before it, with the substep
+ *     lengths held fixed (they are piecewise constant in the state: the
+ *     derivative is that of the branch the forward step took);
+ *   - the transport (Sec. 3.2, eqs. dUdt_sol, glf): the 7-point stencil,
+ *     linearised at U_a with the M1 flux Jacobian (Sec. 2, eqs. edd2,
+ *     eddTens) in closed form;
+ *   - the injection (Sec. 3.1, eq. injnum).
+ * The caller drives the checkpointing: it restores U_k, calls
+ * rt_step_record (which advances the bound state by one step exactly as
+ * rt_step does, split into kernels, and writes a tape), then, later and in
+ * reverse step order, rt_step_adjoint with that tape.
+ * --------------------------------------------------------------------- */
+
+/* Per-step tape, caller-owned device memory.
+ *   Na      ncell doubles: N after the step's injection (the transport input)
+ *   Fa      3*ncell doubles: F after injection, layout [axis][cell]
+ *   counts  ncell int32: accepted chemistry substeps of each cell in this
+ *           step, as rt_step writes them to rt_state.nacc (input)
+ *   off     rt_tape_offsets_len() int64: trace offsets (written by record)
+ *   trace   7*cap doubles: per cell, the state {N, Fx, Fy, Fz, x_HII, T_mu
+ *           (T when isothermal), h} before each accepted substep, then the
+ *           state after the chemistry
+ *   cap     trace entries; must be >= ncell + sum(counts) */
+typedef struct {
+    double *Na, *Fa;
+    const int32_t *counts;
+    int64_t *off;
+    double *trace;
+    long long cap;
+} rt_tape;
+
+/* Adjoint state (device, caller-owned), updated in place from lambda_k+1 =
+ * dL/dU_k+1 to lambda_k = dL/dU_k:
+ *   N (ncell), F (3*ncell, [axis][cell]), xHII (ncell), T (ncell);
+ *   wN (ncell) and wF (3*ncell) are work arrays. */
+typedef struct {
+    double *N, *F, *xHII, *T;
+    double *wN, *wF;
+} rt_adj;
+
+/* int64 entries of rt_tape.off for this grid: ncell + 1 offsets plus one
+ * partial sum per 1024 cells. */
+size_t rt_tape_offsets_len(const rt_ctx *ctx);
+
+/* One forward step (as rt_step with nsteps = 1, same result) that writes the
+ * tape.  tape->counts must hold this step's substep counts (from a previous
+ * rt_step of the same state with rt_state.nacc bound); a mismatch or a too
+ * small cap sets RT_FLAG_TRACE in rt_stats.flags.  dt as for rt_transport. */
+rt_status rt_step_record(rt_ctx *ctx, double dt, const rt_tape *tape);
+
+/* A forward step whose chemistry replays the substep schedule of a recorded
+ * step (per cell: the number of accepted substeps and their lengths from
+ * tape, applied to the current state without the 10% checks of App. A).
+ * Its result is a smooth function of the inputs and parameters, and its
+ * derivative is the one rt_step_adjoint computes: finite differences of
+ * replayed runs check the adjoint without the jumps that a changed substep
+ * schedule puts into finite differences of rt_step.  Reads tape (counts,
+ * off, trace as written by rt_step_record); advances the bound state. */
+rt_status rt_step_replay(rt_ctx *ctx, double dt, const rt_tape *tape);
+
+/* Reverse of the recorded step: lam from lambda_k+1 to lambda_k; adds the
+ * step's contributions to g_lnNdot[s] (device, one per source in the order
+ * given to rt_set_sources) and g_lnnH[cell] (device, ncell).  Reads the
+ * bound n_H and the tape; does not touch the bound state.  Sources and dt
+ * must be those of the recorded step. */
+rt_status rt_step_adjoint(rt_ctx *ctx, double dt, const rt_tape *tape, const rt_adj *lam, double *g_lnNdot,
+                          double *g_lnnH);
 
 #ifdef __cplusplus
 }

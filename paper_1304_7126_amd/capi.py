@@ -15,7 +15,7 @@ RT_OK, RT_EINVAL, RT_EHIP, RT_ENOMEM, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3
 RT_BC_PERIODIC, RT_BC_OUTFLOW, RT_BC_REFLECT = 0, 1, 2
 RT_FLUX_GLF, RT_FLUX_HLL = 0, 1
 RT_PREC_FP64, RT_PREC_FP32_TRANSPORT = 0, 1
-RT_FLAG_CAP, RT_FLAG_NAN, RT_FLAG_NNEG = 1, 2, 8
+RT_FLAG_CAP, RT_FLAG_NAN, RT_FLAG_NNEG, RT_FLAG_TRACE = 1, 2, 8, 16
 
 EXPORTED = [
     "rt_init", "rt_scratch_bytes", "rt_bind", "rt_set_stream", "rt_current", "rt_set_current",
@@ -25,6 +25,7 @@ EXPORTED = [
     "rt_batch_init", "rt_batch_scratch_bytes", "rt_batch_bind", "rt_batch_set_stream", "rt_batch_current",
     "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
+    "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint",
 ]
 
 
@@ -66,6 +67,16 @@ class RtTiming(ctypes.Structure):
 
 
 TIMING_CLASSES = ("inject", "transport", "head", "tail", "other")
+
+
+class RtTape(ctypes.Structure):
+    _fields_ = [("Na", ctypes.c_void_p), ("Fa", ctypes.c_void_p), ("counts", ctypes.c_void_p),
+                ("off", ctypes.c_void_p), ("trace", ctypes.c_void_p), ("cap", ctypes.c_longlong)]
+
+
+class RtAdj(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_void_p), ("F", ctypes.c_void_p), ("xHII", ctypes.c_void_p),
+                ("T", ctypes.c_void_p), ("wN", ctypes.c_void_p), ("wF", ctypes.c_void_p)]
 
 _lib = None
 
@@ -154,6 +165,14 @@ def lib():
     L.rt_batch_last_error.restype = ctypes.c_char_p
     L.rt_batch_free.argtypes = [vp]
     L.rt_batch_free.restype = None
+    L.rt_tape_offsets_len.argtypes = [vp]
+    L.rt_tape_offsets_len.restype = ctypes.c_size_t
+    L.rt_step_record.argtypes = [vp, ctypes.c_double, ctypes.POINTER(RtTape)]
+    L.rt_step_record.restype = st
+    L.rt_step_replay.argtypes = [vp, ctypes.c_double, ctypes.POINTER(RtTape)]
+    L.rt_step_replay.restype = st
+    L.rt_step_adjoint.argtypes = [vp, ctypes.c_double, ctypes.POINTER(RtTape), ctypes.POINTER(RtAdj), vp, vp]
+    L.rt_step_adjoint.restype = st
     _lib = L
     return L
 

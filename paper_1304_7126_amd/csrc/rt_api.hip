@@ -31,6 +31,9 @@ struct rt_ctx {
     int nsrc = 0;
     int32_t *src_cell = nullptr;
     double *src_rate = nullptr;
+    int nsrc_in = 0;                 // sources as given (for the injection adjoint)
+    int32_t *src_in_cell = nullptr;
+    double *src_in_rate = nullptr;   // group-0 rate of each given source
     DevStats *dstats = nullptr;
     RedOut *dred = nullptr;
     unsigned qcap = 0;               // chemistry queue capacity (cells)
@@ -480,8 +483,25 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     }
     if (c->src_cell) { (void)hipFree(c->src_cell); c->src_cell = nullptr; }
     if (c->src_rate) { (void)hipFree(c->src_rate); c->src_rate = nullptr; }
+    if (c->src_in_cell) { (void)hipFree(c->src_in_cell); c->src_in_cell = nullptr; }
+    if (c->src_in_rate) { (void)hipFree(c->src_in_rate); c->src_in_rate = nullptr; }
     c->nsrc = 0;
+    c->nsrc_in = 0;
     if (cells.empty()) return RT_OK;
+    {
+        std::vector<int32_t> in_cell(n);
+        std::vector<double> in_rate(n);
+        for (int s = 0; s < n; ++s) {
+            in_cell[s] = (int32_t)((size_t)ijk[3 * s] +
+                                   (size_t)c->grid.nx * ((size_t)ijk[3 * s + 1] + (size_t)c->grid.ny * ijk[3 * s + 2]));
+            in_rate[s] = ndot[(size_t)s * M];
+        }
+        RT_HIP(c, hipMalloc((void **)&c->src_in_cell, n * sizeof(int32_t)));
+        RT_HIP(c, hipMalloc((void **)&c->src_in_rate, n * sizeof(double)));
+        RT_HIP(c, hipMemcpy(c->src_in_cell, in_cell.data(), n * sizeof(int32_t), hipMemcpyHostToDevice));
+        RT_HIP(c, hipMemcpy(c->src_in_rate, in_rate.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        c->nsrc_in = n;
+    }
     RT_HIP(c, hipMalloc((void **)&c->src_cell, cells.size() * sizeof(int32_t)));
     RT_HIP(c, hipMalloc((void **)&c->src_rate, rates.size() * sizeof(double)));
     RT_HIP(c, hipMemcpy(c->src_cell, cells.data(), cells.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -685,6 +705,98 @@ extern "C" rt_status rt_get_timing(rt_ctx *c, rt_timing *out)
     return RT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Differentiation form: record and reverse one step.
+// ---------------------------------------------------------------------------
+static rt_status adj_supported(rt_ctx *c, double dt)
+{
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    if (c->groups.M != 1) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs one photon group (M = %d)", c->groups.M);
+    if (c->params.Y != 0.0) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs hydrogen-only gas (Y = 0)");
+    if (c->params.flux != RT_FLUX_GLF) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the GLF flux");
+    if (c->fp32) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs RT_PREC_FP64");
+    for (int f = 0; f < 6; ++f)
+        if (c->grid.bc[f] != RT_BC_PERIODIC) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs periodic boundaries");
+    const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
+    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    return RT_OK;
+}
+
+static rt_status tape_ok(rt_ctx *c, const rt_tape *t)
+{
+    if (!t || !t->Na || !t->Fa || !t->counts || !t->off || !t->trace)
+        RT_FAIL(c, RT_EINVAL, "tape arrays must be non-null");
+    if (t->cap < (long long)c->grid.ncell) RT_FAIL(c, RT_EINVAL, "tape cap %lld < ncell", t->cap);
+    return RT_OK;
+}
+
+extern "C" size_t rt_tape_offsets_len(const rt_ctx *c)
+{
+    if (!c) return 0;
+    return c->grid.ncell + 1 + adj_scan_parts(c->grid.ncell);
+}
+
+extern "C" rt_status rt_step_record(rt_ctx *c, double dt, const rt_tape *t)
+{
+    if (!c) return RT_EINVAL;
+    rt_status r = adj_supported(c, dt);
+    if (r != RT_OK) return r;
+    if ((r = tape_ok(c, t)) != RT_OK) return r;
+    const size_t nc = c->grid.ncell;
+    RT_HIP(c, launch_offsets(t->counts, nc, t->off, c->stream));
+    if ((r = do_inject(c, dt)) != RT_OK) return r;
+    RT_HIP(c, hipMemcpyAsync(t->Na, c->st.N[c->cur], nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    RT_HIP(c, hipMemcpyAsync(t->Fa, c->st.F[c->cur], 3 * nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if ((r = do_transport(c, dt)) != RT_OK) return r;
+    return timed(c, TM_OTHER, [&]() -> rt_status {
+        RT_HIP(c, launch_chem_record(c->dkchem, nc, dt, (double *)c->st.N[c->cur], (double *)c->st.F[c->cur],
+                                     c->st.xHII, c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace, c->dstats,
+                                     c->stream));
+        return RT_OK;
+    });
+}
+
+extern "C" rt_status rt_step_replay(rt_ctx *c, double dt, const rt_tape *t)
+{
+    if (!c) return RT_EINVAL;
+    rt_status r = adj_supported(c, dt);
+    if (r != RT_OK) return r;
+    if ((r = tape_ok(c, t)) != RT_OK) return r;
+    const size_t nc = c->grid.ncell;
+    if ((r = do_inject(c, dt)) != RT_OK) return r;
+    if ((r = do_transport(c, dt)) != RT_OK) return r;
+    return timed(c, TM_OTHER, [&]() -> rt_status {
+        RT_HIP(c, launch_chem_replay(c->dkchem, nc, (double *)c->st.N[c->cur], (double *)c->st.F[c->cur], c->st.xHII,
+                                     c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace, c->stream));
+        return RT_OK;
+    });
+}
+
+extern "C" rt_status rt_step_adjoint(rt_ctx *c, double dt, const rt_tape *t, const rt_adj *lam, double *g_lnNdot,
+                                     double *g_lnnH)
+{
+    if (!c) return RT_EINVAL;
+    rt_status r = adj_supported(c, dt);
+    if (r != RT_OK) return r;
+    if ((r = tape_ok(c, t)) != RT_OK) return r;
+    if (!lam || !lam->N || !lam->F || !lam->xHII || !lam->T || !lam->wN || !lam->wF)
+        RT_FAIL(c, RT_EINVAL, "adjoint arrays must be non-null");
+    if (!g_lnnH) RT_FAIL(c, RT_EINVAL, "g_lnnH must be non-null");
+    if (c->nsrc_in > 0 && !g_lnNdot) RT_FAIL(c, RT_EINVAL, "g_lnNdot must be non-null when there are sources");
+    const size_t nc = c->grid.ncell;
+    const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+    return timed(c, TM_OTHER, [&]() -> rt_status {
+        RT_HIP(c, launch_chem_adj(c->dkchem, nc, c->st.nH, t->counts, t->off, t->cap, t->trace, lam->N, lam->F,
+                                  lam->xHII, lam->T, lam->wN, lam->wF, g_lnnH, c->stream));
+        RT_HIP(c, launch_transport_adj(c->grid, c->groups.c_r, dt / c->grid.dx, t->Na, t->Fa, lam->wN, lam->wF, lam->N,
+                                       lam->F, c->stream));
+        RT_HIP(c, launch_inject_adj(lam->N, c->nsrc_in, c->src_in_cell, c->src_in_rate, dt / V, g_lnNdot,
+                                    c->stream));
+        return RT_OK;
+    });
+}
+
 extern "C" const char *rt_last_error(const rt_ctx *c)
 {
     if (!c) return g_init_err.c_str();
@@ -699,6 +811,8 @@ extern "C" void rt_free(rt_ctx *c)
     if (c->hll_dev) (void)hipFree(c->hll_dev);
     if (c->src_cell) (void)hipFree(c->src_cell);
     if (c->src_rate) (void)hipFree(c->src_rate);
+    if (c->src_in_cell) (void)hipFree(c->src_in_cell);
+    if (c->src_in_rate) (void)hipFree(c->src_in_rate);
     if (c->dstats) (void)hipFree(c->dstats);
     if (c->dred) (void)hipFree(c->dred);
     if (c->dkchem) (void)hipFree(c->dkchem);

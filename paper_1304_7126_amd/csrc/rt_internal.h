@@ -99,4 +99,21 @@ hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, con
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,
                          hipStream_t s);
 
+// differentiation form (rt_adjoint.hip)
+size_t adj_scan_parts(size_t nc);
+hipError_t launch_offsets(const int32_t *counts, size_t nc, int64_t *off, hipStream_t s);
+hipError_t launch_chem_record(const KChem *dk, size_t nc, double dt, double *N, double *F, double *xHII, double *T,
+                              const double *nH, const int32_t *counts, const int64_t *off, long long cap,
+                              double *trace, DevStats *st, hipStream_t s);
+hipError_t launch_chem_replay(const KChem *dk, size_t nc, double *N, double *F, double *xHII, double *T,
+                              const double *nH, const int32_t *counts, const int64_t *off, long long cap,
+                              const double *trace, hipStream_t s);
+hipError_t launch_chem_adj(const KChem *dk, size_t nc, const double *nH, const int32_t *counts, const int64_t *off,
+                           long long cap, const double *trace, const double *lN, const double *lF, double *lx,
+                           double *lT, double *wN, double *wF, double *g, hipStream_t s);
+hipError_t launch_transport_adj(const KGrid &g, double c, double kdx, const double *Na, const double *Fa,
+                                const double *lNb, const double *lFb, double *lNa, double *lFa, hipStream_t s);
+hipError_t launch_inject_adj(const double *lN, int nsrc, const int32_t *cell, const double *ndot, double dtV,
+                             double *g, hipStream_t s);
+
 }  // namespace rtm1

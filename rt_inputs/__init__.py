@@ -107,7 +107,7 @@ def lognormal_nH(n: Sequence[int], sigma_ln: float, mean: float, seed: int) -> n
     amp = np.zeros_like(k)
     nz_mask = k > 0
     amp[nz_mask] = k[nz_mask] ** -1.5
-    d = np.fft.irfftn(wk * amp, s=(nz, ny, nx))
+    d = np.fft.irfftn(wk * amp, s=(nz, ny, nx), axes=(0, 1, 2))
     d -= d.mean()
     sd = d.std()
     if sd > 0:
@@ -194,14 +194,32 @@ def lognormal_256(steps: int = 100, seed: int = 0) -> Workload:
     return lognormal_box(256, 13.2, 200, steps, seed)
 
 
-def grey_64(steps: int = 300, seed: int = 0) -> Workload:
-    """64^3 periodic H-only box, one grey group of a 1e5 K blackbody,
-    lognormal density with sigma_ln = 0.8, 16 sources, GLF."""
-    w = lognormal_box(64, 3.3, 16, steps, seed, flux=FLUX_GLF,
+def grey_box(n: int, L_kpc: float, n_sources: int, steps: int, seed: int = 0, isothermal: bool = False,
+             sigma_ln: float = 0.8) -> Workload:
+    """Periodic hydrogen-only box (X = 1, Y = 0) with one grey group
+    [13.6 eV, inf) of a 1e5 K blackbody, lognormal density (mean 1e-3,
+    sigma_ln), K random sources, GLF.  Isothermal: the gas of the Stromgren
+    test (T = 1e4 K fixed, x_HII = 1.2e-3); otherwise T evolves from 100 K
+    with x_HII = 1e-6."""
+    w = lognormal_box(n, L_kpc, n_sources, steps, seed, flux=FLUX_GLF,
                       spectrum=Spectrum(kind="bb", T_bb=1e5, edges_eV=EDGES_1),
-                      sigma_ln=0.8, name="grey_64")
+                      sigma_ln=sigma_ln, name=f"grey_{n}")
     w.X, w.Y = 1.0, 0.0
+    if isothermal:
+        w.isothermal, w.T0, w.xHII0 = True, 1e4, 1.2e-3
     return w
+
+
+def grey_64(steps: int = 300, seed: int = 0, isothermal: bool = False) -> Workload:
+    """The differentiation workload: 64^3, 3.3 kpc, 16 sources, sigma_ln = 0.8."""
+    return grey_box(64, 3.3, 16, steps, seed, isothermal=isothermal)
+
+
+def perturbed_log_rates(ndot: np.ndarray, seed: int, scale: float = 0.1) -> np.ndarray:
+    """ln(Ndot) + scale * xi, xi ~ N(0, 1) per source (seed + 3000): the
+    source rates of the run that makes the target of the gradient tests."""
+    rng = np.random.default_rng(seed + 3000)
+    return np.log(np.asarray(ndot, np.float64)) + scale * rng.standard_normal(len(ndot))
 
 
 @dataclasses.dataclass

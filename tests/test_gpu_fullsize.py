@@ -57,19 +57,31 @@ def test_256_cubed_sampled_cells_match_oracle(fp32):
     assert flip <= 5e-3, flip
     assert int(r["natt"].max()) > 10  # the sample contains subcycling cells
     tol = 1e-5 if fp32 else 1e-10
+    # Near full ionisation x_HI = 1 - x is ill-conditioned: x agrees to a few
+    # ulps (~1e-16 absolute), so x_HI and with it the absorption factor
+    # 1/(1 + h c sigma n_HI) of every substep differ by ~1e-16/x_HI relative;
+    # over the step's optical depth (<~ 100) N and F pick up ~1e-14/x_HI.
+    xhi = np.maximum(1.0 - r["x"][:, 0], 1e-6)
+    rtol = tol + 1e-14 / xhi
     for gi in range(M):
         sc = np.max(np.abs(r["N"][:, gi]))
         err = np.abs(gN[same, gi] - r["N"][same, gi])
-        assert np.all(err <= tol * np.abs(r["N"][same, gi]) + tol * 1e-3 * sc), (gi, err.max())
+        lim = rtol[same] * np.abs(r["N"][same, gi]) + tol * 1e-3 * sc
+        w = np.argmax(err / lim)
+        print(f"N{gi}: worst err/limit {err[w] / lim[w]:.3g} (x_HI {xhi[same][w]:.3g})", flush=True)
+        assert np.all(err <= lim), (gi, err.max())
         # flux components are compared on the scale of the cell's |F|
         Fn = np.linalg.norm(r["F"][same, gi], axis=1)
         scF = np.max(np.linalg.norm(r["F"][:, gi], axis=1))
         errF = np.linalg.norm(gF[same, gi] - r["F"][same, gi], axis=1)
-        assert np.all(errF <= tol * Fn + tol * 1e-3 * scF), (gi, errF.max())
+        limF = rtol[same] * Fn + tol * 1e-3 * scF
+        w = np.argmax(errF / limF)
+        print(f"F{gi}: worst err/limit {errF[w] / limF[w]:.3g} (|F| {Fn[w]:.3g}, x_HI {xhi[same][w]:.3g})", flush=True)
+        assert np.all(errF <= limF), (gi, errF.max())
     for q in range(3):
         err = np.abs(gx[same, q] - r["x"][same, q])
         assert np.all(err <= tol * np.abs(r["x"][same, q]) + 1e-15), (q, err.max())
     assert np.all(np.abs(gT[same] - r["T"][same]) <= tol * r["T"][same])
-    # x_HI = 1 - x_HII near full ionisation
+    # x_HI = 1 - x near full ionisation
     xhi_err = np.abs((1 - gx[same, 0]) - (1 - r["x"][same, 0]))
     assert np.all(xhi_err <= tol * 1e3 * np.maximum(1 - r["x"][same, 0], 1e-6))
