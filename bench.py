@@ -184,7 +184,7 @@ def adjoint_cost(steps=300, every=20):
     return {"workload": f"grey {w.n[0]}^3 x 1 group, H only, 16 sources, {steps} steps, checkpoints every {every}, "
                         "GLF, FP64",
             "forward_ms": tp * 1e3, "forward_checkpointed_ms": tf * 1e3, "backward_ms": tb * 1e3,
-            "ratio": tb / tp, "ratio_with_forward": (tf + tb) / tp,
+            "ratio": (tf + tb) / tp, "backward_only_ratio": tb / tp,
             "trace_entries_max": run.last_backward.get("trace_entries_max"),
             "grad_finite": bool(torch.isfinite(g_src).all().item() and torch.isfinite(g_nH).all().item())}
 
@@ -198,7 +198,8 @@ def main():
         return bench_batch(args)
     if args.form == "adjoint":
         a = adjoint_cost()
-        print(json.dumps({"metric": "adjoint/forward cost ratio", "value": a["ratio"], "unit": "x",
+        print(json.dumps({"metric": "adjoint/forward cost ratio (checkpointed forward + reverse sweep over plain "
+                          "forward)", "value": a["ratio"], "unit": "x",
                           "n_gpus": 1, "steps": 300, "warmup": 1, "ms_per_step": a["backward_ms"] / 300,
                           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
                           "data": "synthetic", "config": {"workload": a["workload"]}, "adjoint": a}), flush=True)

@@ -255,7 +255,7 @@ rt_status rt_batch_init(int nbox, const rt_grid *grids, const rt_groups *groups,
                         rt_batch **out);
 
 /* Device scratch the batch needs (chunk counter and the queue of cells still
- * subcycling, sized for an eighth of all cells). */
+ * subcycling, with room for every cell). */
 size_t rt_batch_scratch_bytes(const rt_batch *b);
 
 /* states[nbox]: caller-owned arrays of every box as for rt_bind (the scratch

@@ -294,33 +294,31 @@ __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ k
     double *tr = trace + (size_t)TV * (size_t)o;
     CS s;
     s.N[0] = N[i];
-    s.F[0][0] = F[i];
-    s.F[0][1] = F[nc + i];
-    s.F[0][2] = F[2 * nc + i];
     s.N[1] = s.N[2] = 0.0;
-    for (int g = 1; g < 3; ++g) s.F[g][0] = s.F[g][1] = s.F[g][2] = 0.0;
+    s.fs[1] = s.fs[2] = 1.0;
+    const double F0[3] = {F[i], F[nc + i], F[2 * nc + i]};
     s.x = xHII[i];
     s.y2 = 0.0;
     s.y3 = 0.0;
-    const double Tiso = T[i];
-    const double nh = nH[i];
+    const CC cc = make_cc(k, nH[i], T[i]);
     unsigned fl = 0;
-    const bool ok = chem_init<1>(k, dt, Tiso, s);
+    const bool ok =
+        chem_init<CM>(k, dt, cc.Tiso, isfinite(F0[0]) && isfinite(F0[1]) && isfinite(F0[2]), s);
     bool done = !ok;
     int n = 0;
     while (!done) {
-        const double e0 = s.N[0], e1 = s.F[0][0], e2 = s.F[0][1], e3 = s.F[0][2], e4 = s.x;
-        const double e5 = k.isothermal ? Tiso : s.Tmu;
+        const double e0 = s.N[0], e4 = s.x, fs = s.fs[0];
+        const double e5 = k.isothermal ? cc.Tiso : s.Tmu;
         const double h = s.h >= s.rem * (1.0 - 1e-10) ? s.rem : s.h;  // the length chem_attempt takes
         const int acc0 = s.acc;
-        done = chem_attempt<1>(k, nh, Tiso, s, fl);
+        done = chem_attempt<CM>(k, cc, s, fl);
         if (s.acc != acc0) {
             if (fits && n < cnt) {
                 double *e = tr + TV * n;
                 e[0] = e0;
-                e[1] = e1;
-                e[2] = e2;
-                e[3] = e3;
+                e[1] = F0[0] * fs;
+                e[2] = F0[1] * fs;
+                e[3] = F0[2] * fs;
                 e[4] = e4;
                 e[5] = e5;
                 e[6] = h;
@@ -332,19 +330,19 @@ __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ k
     if (fits) {
         double *e = tr + TV * cnt;
         e[0] = s.N[0];
-        e[1] = s.F[0][0];
-        e[2] = s.F[0][1];
-        e[3] = s.F[0][2];
+        e[1] = F0[0] * s.fs[0];
+        e[2] = F0[1] * s.fs[0];
+        e[3] = F0[2] * s.fs[0];
         e[4] = s.x;
-        e[5] = k.isothermal ? Tiso : s.Tmu;
+        e[5] = k.isothermal ? cc.Tiso : s.Tmu;
         e[6] = (double)(n < cnt ? n : cnt);
     }
     if (ok) {
-        const double Tout = chem_finish<1>(k, Tiso, s, fl);
+        const double Tout = chem_finish<CM>(k, cc, s, fl);
         N[i] = s.N[0];
-        F[i] = s.F[0][0];
-        F[nc + i] = s.F[0][1];
-        F[2 * nc + i] = s.F[0][2];
+        F[i] = F0[0] * s.fs[0];
+        F[nc + i] = F0[1] * s.fs[0];
+        F[2 * nc + i] = F0[2] * s.fs[0];
         xHII[i] = s.x;
         T[i] = Tout;
     } else {

@@ -400,10 +400,9 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     }
     memset(&c->st, 0, sizeof(c->st));
     {
-        // queue for the cells still subcycling after the head pass: an
-        // eighth of the grid (cells beyond it finish in the head pass)
-        size_t cap = c->grid.ncell / 8;
-        if (cap < 4096) cap = c->grid.ncell < 4096 ? c->grid.ncell : 4096;
+        // queue for the cells still subcycling after the head pass: room
+        // for every cell, so that no cell has to finish in the head pass
+        const size_t cap = c->grid.ncell;
         c->qcap = (unsigned)cap;
         c->qcap_max = (unsigned)cap;
     }

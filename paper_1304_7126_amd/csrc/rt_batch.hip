@@ -44,7 +44,7 @@ struct BSrc {
     double rate[3];
 };
 
-// scratch: [3 counters + pad: 256 B][cell, box, acc, att: 4 x cap int32][18 x cap doubles]
+// scratch: [3 counters + pad: 256 B][cell, box, acc, att: 4 x cap int32][QV x cap doubles]
 struct BQueue {
     unsigned *ctr;  // [0] chunks taken, [1] cells queued, [2] queued cells taken
     int32_t *cell, *box, *acc, *att;
@@ -84,15 +84,14 @@ __device__ __forceinline__ void bq_store(const BQueue &q, unsigned stride, uint3
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         v[(size_t)g * c] = s.N[g];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[(size_t)(3 + 3 * g + d) * c] = s.F[g][d];
+        v[(size_t)(3 + g) * c] = s.fs[g];
     }
-    v[12 * c] = s.x;
-    v[13 * c] = s.y2;
-    v[14 * c] = s.y3;
-    v[15 * c] = s.Tmu;
-    v[16 * c] = s.rem;
-    v[17 * c] = s.h;
+    v[6 * c] = s.x;
+    v[7 * c] = s.y2;
+    v[8 * c] = s.y3;
+    v[9 * c] = s.Tmu;
+    v[10 * c] = s.rem;
+    v[11 * c] = s.h;
 }
 
 __device__ __forceinline__ void bq_load(const BQueue &q, unsigned stride, uint32_t p, uint32_t &box, uint32_t &cell,
@@ -107,18 +106,18 @@ __device__ __forceinline__ void bq_load(const BQueue &q, unsigned stride, uint32
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         s.N[g] = v[(size_t)g * c];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) s.F[g][d] = v[(size_t)(3 + 3 * g + d) * c];
+        s.fs[g] = v[(size_t)(3 + g) * c];
     }
-    s.x = v[12 * c];
-    s.y2 = v[13 * c];
-    s.y3 = v[14 * c];
-    s.Tmu = v[15 * c];
-    s.rem = v[16 * c];
-    s.h = v[17 * c];
+    s.x = v[6 * c];
+    s.y2 = v[7 * c];
+    s.y3 = v[8 * c];
+    s.Tmu = v[9 * c];
+    s.rem = v[10 * c];
+    s.h = v[11 * c];
 }
 
-// write the finished state of a cell of a box with M groups (runtime M)
+// write the finished state of a cell of a box with M groups (runtime M); the
+// transported flux in the destination is rescaled by fs
 template <typename R>
 __device__ __forceinline__ void bstore(const BoxDev &b, int dst, uint32_t i, const CS &s, double T)
 {
@@ -127,7 +126,10 @@ __device__ __forceinline__ void bstore(const BoxDev &b, int dst, uint32_t i, con
     R *F = (R *)b.F[dst];
     for (int g = 0; g < b.M; ++g) {
         N[(size_t)g * nc + i] = (R)s.N[g];
-        for (int d = 0; d < 3; ++d) F[(size_t)(3 * g + d) * nc + i] = (R)s.F[g][d];
+        for (int d = 0; d < 3; ++d) {
+            R &f = F[(size_t)(3 * g + d) * nc + i];
+            f = (R)((double)f * s.fs[g]);
+        }
     }
     b.xHII[i] = s.x;
     b.xHeII[i] = s.y2;
@@ -170,12 +172,12 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
     const bool valid = i < (uint32_t)b.g.ncell;
     const size_t nc = b.g.ncell;
     CS s;
-    double nH = 1.0, Tiso = 0.0;
+    CC cc{1.0, 0.0, 0.0, 0.0};
     bool done = true;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         s.N[g] = 0.0;
-        s.F[g][0] = s.F[g][1] = s.F[g][2] = 0.0;
+        s.fs[g] = 1.0;
     }
     if (valid) {
         int ix, iy, iz;
@@ -183,23 +185,25 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
         const Nbr nb = neighbours(b.g, i, ix, iy, iz);
         const R *Nin = (const R *)b.N[src];
         const R *Fin = (const R *)b.F[src];
+        R *Fout = (R *)b.F[1 - src];
+        bool fin = true;
 #pragma unroll
         for (int grp = 0; grp < M; ++grp) {
             const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc, Fin + (size_t)3 * grp * nc, c,
                                                     (R)b.kdx, tab, nf, nth);
             s.N[grp] = (double)o.n;
-            s.F[grp][0] = (double)o.fx;
-            s.F[grp][1] = (double)o.fy;
-            s.F[grp][2] = (double)o.fz;
+            Fout[(size_t)(3 * grp) * nc + i] = o.fx;
+            Fout[(size_t)(3 * grp + 1) * nc + i] = o.fy;
+            Fout[(size_t)(3 * grp + 2) * nc + i] = o.fz;
+            fin = fin && isfinite(o.fx) && isfinite(o.fy) && isfinite(o.fz);
         }
         s.x = b.xHII[i];
         s.y2 = b.xHeII[i];
         s.y3 = b.xHeIII[i];
-        Tiso = b.T[i];
-        nH = b.nH[i];
-        if (chem_init<M>(k, dt, Tiso, s)) {
+        cc = make_cc(k, b.nH[i], b.T[i]);
+        if (chem_init<CM>(k, dt, cc.Tiso, fin, s)) {
             done = false;
-            for (int a = 0; a < K && !done; ++a) done = chem_attempt<M>(k, nH, Tiso, s, fl);
+            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM>(k, cc, s, fl);
         } else {
             fl |= 2u;
         }
@@ -221,10 +225,10 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
         }
     }
     if (want && !queued) {
-        while (!done) done = chem_attempt<M>(k, nH, Tiso, s, fl);
+        while (!done) done = chem_attempt<CM>(k, cc, s, fl);
     }
     if (valid && !queued) {
-        const double T = chem_finish<M>(k, Tiso, s, fl);
+        const double T = chem_finish<CM>(k, cc, s, fl);
         bstore<R>(b, 1 - src, i, s, T);
         a_acc += (unsigned long long)s.acc;
         a_att += (unsigned long long)s.att;
@@ -288,9 +292,8 @@ __global__ __launch_bounds__(256) void k_bhead(const BoxDev *__restrict__ boxes,
     bblock_stats(st, a_acc, a_att, a_max, fl);
 }
 
-// Tail: lanes hold cells of any box.  The attempt runs with three groups;
-// the groups a box does not have carry zero photons and zero cross sections,
-// which leaves every sum and check exactly as with the box's own M.
+// Tail: lanes hold cells of any box (the attempt runs with three groups, as
+// in every chemistry kernel).
 template <typename R>
 __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes, BQueue q, unsigned stride, int dst,
                                                double dt, DevStats *__restrict__ st)
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
     const unsigned n = min(q.ctr[1], q.cap);
     CS s;
     uint32_t cell = 0, box = 0;
-    double nH = 1.0, Tiso = 0.0;
+    CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
     unsigned fl = 0;
     unsigned long long a_acc = 0, a_att = 0, a_max = 0;
@@ -317,8 +320,7 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
                     const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
                     if (p < n) {
                         bq_load(q, stride, p, box, cell, s);
-                        nH = boxes[box].nH[cell];
-                        Tiso = boxes[box].T[cell];
+                        cc = make_cc(*boxes[box].kchem, boxes[box].nH[cell], boxes[box].T[cell]);
                         active = true;
                     }
                 }
@@ -327,8 +329,8 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
         if (!__any(active)) break;
         if (active) {
             const KChem &k = *boxes[box].kchem;
-            if (chem_attempt<3>(k, nH, Tiso, s, fl)) {
-                const double T = chem_finish<3>(k, Tiso, s, fl);
+            if (chem_attempt<CM>(k, cc, s, fl)) {
+                const double T = chem_finish<CM>(k, cc, s, fl);
                 bstore<R>(boxes[box], dst, cell, s, T);
                 a_acc += (unsigned long long)s.acc;
                 a_att += (unsigned long long)s.att;
@@ -510,8 +512,8 @@ extern "C" rt_status rt_batch_init(int nbox, const rt_grid *grids, const rt_grou
     for (int i : order)
         for (size_t s = 0; s < b->boxes[i].g.ncell; s += 64) chunks.push_back({(uint32_t)i, (uint32_t)s});
     b->nchunks = (unsigned)chunks.size();
-    size_t cap = ncell_tot / 8;
-    if (cap < 4096) cap = ncell_tot < 4096 ? ncell_tot : 4096;
+    // room for every cell, so that no cell has to finish in the head pass
+    const size_t cap = ncell_tot;
     b->qcap = b->qcap_max = (unsigned)cap;
 
     std::vector<double> tab((size_t)b->nf * b->nth * 2);

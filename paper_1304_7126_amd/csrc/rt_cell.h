@@ -176,24 +176,55 @@ __device__ __forceinline__ double mu_of(const KChem &k, double x, double y2, dou
     return 1.0 / (k.X * (1.0 + x) + 0.25 * k.Y * (1.0 + y2 + 2.0 * y3));
 }
 
-__device__ __forceinline__ double rel_change(double a, double b) { return fabs(a - b) / b; }
+// |a - b| > f b for b > 0: the relative-change test of App. A without a division
+__device__ __forceinline__ bool rel_above(double a, double b, double f) { return fabs(a - b) > f * b; }
 
-// Thermochemical state of one cell during its subcycling over dt_RT.
+// Thermochemical state of one cell during its subcycling over dt_RT.  The
+// flux of a group only scales with the absorption factor of each accepted
+// substep, so the state carries that product (fs) and the flux itself stays
+// in the destination arrays until the cell has finished.
 struct CS {
-    double N[3], F[3][3];
+    double N[3], fs[3];
     double x, y2, y3, Tmu;
     double rem, h;  // time left in dt_RT, length of the next substep
     int acc, att;   // accepted substeps, attempts
 };
 
-// Returns false (and leaves the cell untouched) when an input is not finite.
-template <int M>
-__device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, CS &s)
+// Every chemistry kernel runs the attempt with three groups; groups a grid
+// does not have carry zero photons and zero cross sections, which leaves
+// every sum and check exactly as with fewer groups.  One instantiation for
+// all kernels keeps their arithmetic identical, so that a cell's result does
+// not depend on which kernel (first pass, queue, batch, tape) finishes it.
+constexpr int CM = 3;
+
+// Per-cell constants of the chemistry: n_H, n_He, the factor K of the
+// T_mu equation (eq. ramsesrt_cool1_eq) and the fixed temperature of
+// isothermal runs.
+struct CC {
+    double nH, nHe, K, Tiso;
+};
+
+__device__ __forceinline__ CC make_cc(const KChem &k, double nH, double T)
 {
-    bool ok = isfinite(T) && isfinite(s.x) && isfinite(s.y2) && isfinite(s.y3);
+    CC c;
+    c.nH = nH;
+    c.nHe = nH * k.Y / (4.0 * k.X);
+    c.K = k.Kfac / nH;
+    c.Tiso = T;
+    return c;
+}
+
+// Returns false (and leaves the cell untouched) when an input is not finite;
+// fin says whether the cell's fluxes are finite.
+template <int M>
+__device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, bool fin, CS &s)
+{
+    bool ok = fin && isfinite(T) && isfinite(s.x) && isfinite(s.y2) && isfinite(s.y3);
 #pragma unroll
-    for (int g = 0; g < M; ++g)
-        ok = ok && isfinite(s.N[g]) && isfinite(s.F[g][0]) && isfinite(s.F[g][1]) && isfinite(s.F[g][2]);
+    for (int g = 0; g < M; ++g) {
+        ok = ok && isfinite(s.N[g]);
+        s.fs[g] = 1.0;
+    }
     s.Tmu = T / mu_of(k, s.x, s.y2, s.y3);
     s.rem = ok ? dt : 0.0;
     s.h = dt;
@@ -204,11 +235,11 @@ __device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, C
 
 // One attempt of a substep of length h (App. A tasks 1-5).  On a failed
 // 10% check the state is unchanged and h is halved; on success the state
-// advances by h, and the next h doubles when the largest relative change
-// was below 5%.  Returns true when the cell has filled dt_RT (or reached
-// the attempt cap, flag bit 0).
+// advances by h, and the next h doubles when every relative change was
+// below 5%.  Returns true when the cell has filled dt_RT (or reached the
+// attempt cap, flag bit 0).
 template <int M>
-__device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double Tiso, CS &s, unsigned &flags)
+__device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s, unsigned &flags)
 {
     if (s.att >= k.max_att) {
         flags |= 1u;
@@ -216,31 +247,28 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double T
     }
     ++s.att;
     const bool iso = k.isothermal != 0;
-    const double nHe = nH * k.Y / (4.0 * k.X);
-    const double K = k.Kfac / nH;
+    const double nH = cc.nH, nHe = cc.nHe, K = cc.K;
     double h = s.h;
     if (h >= s.rem * (1.0 - 1e-10)) h = s.rem;
     const double x = s.x, y2 = s.y2, y3 = s.y3, Tmu = s.Tmu;
-    double maxrel = 0.0, r;
+    bool small = true;  // every relative change below 5%
     // ---- photons: semi-implicit absorption with backward abundances
     const double nHI = (1.0 - x) * nH;
     const double nHeI = (1.0 - y2 - y3) * nHe;
     const double nHeII = y2 * nHe;
     const double nHII = x * nH;
     const double nHeIII = y3 * nHe;
-    double Nn[M], Fn[M][3];
+    double Nn[M], rd[M];
     bool fail = false;
 #pragma unroll
     for (int g = 0; g < M; ++g) {
         const double D = k.cr * (k.sN[g][0] * nHI + k.sN[g][1] * nHeI + k.sN[g][2] * nHeII);
-        const double rden = 1.0 / (1.0 + h * D);
-        Nn[g] = s.N[g] * rden;
-        Fn[g][0] = s.F[g][0] * rden;
-        Fn[g][1] = s.F[g][1] * rden;
-        Fn[g][2] = s.F[g][2] * rden;
-        r = s.N[g] > k.N_floor ? rel_change(Nn[g], s.N[g]) : 0.0;
-        fail |= r > 0.1;
-        maxrel = r > maxrel ? r : maxrel;
+        rd[g] = 1.0 / (1.0 + h * D);
+        Nn[g] = s.N[g] * rd[g];
+        if (s.N[g] > k.N_floor) {
+            fail |= rel_above(Nn[g], s.N[g], 0.1);
+            small &= fabs(Nn[g] - s.N[g]) < 0.05 * s.N[g];
+        }
     }
     if (fail) {
         s.h = 0.5 * h;
@@ -274,12 +302,11 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double T
             return false;
         }
         Tmun = Tmu + Lam * K * h / den;
-        r = rel_change(Tmun, Tmu);
-        if (r > 0.1 || fabs(K * Lam * h) / Tmu > 0.1) {
+        if (rel_above(Tmun, Tmu, 0.1) || fabs(K * Lam * h) > 0.1 * Tmu) {
             s.h = 0.5 * h;
             return false;
         }
-        maxrel = r > maxrel ? r : maxrel;
+        small &= fabs(Tmun - Tmu) < 0.05 * Tmu;
     }
     // ---- hydrogen: semi-implicit in x_HII
     double GHI = 0.0, GHeI = 0.0, GHeII = 0.0;
@@ -289,7 +316,7 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double T
         GHeI += k.sN[g][1] * k.cr * Nn[g];
         GHeII += k.sN[g][2] * k.cr * Nn[g];
     }
-    const Tq q1 = make_Tq(iso ? Tiso : Tmun * mu0);
+    const Tq q1 = make_Tq(iso ? cc.Tiso : Tmun * mu0);
     const vd bH = beta_HI(q1);
     const vd aH = alphaB_HII(q1);
     const double Cr = bH.v * ne0 + GHI;
@@ -312,24 +339,23 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double T
     const double rate = Cr - x * (Cr + Dr);
     double xn = x + h * rate / denx;
     xn = xn < k.x_min ? k.x_min : (xn > 1.0 ? 1.0 : xn);
-    r = rel_change(xn, x);
-    if (r > 0.1 || fabs(rate) * h / x > 0.1) {
+    if (rel_above(xn, x, 0.1) || fabs(rate) * h > 0.1 * x) {
         s.h = 0.5 * h;
         return false;
     }
-    maxrel = r > maxrel ? r : maxrel;
+    small &= fabs(xn - x) < 0.05 * x;
     // ---- helium: HeI, HeII, HeIII in order, then He conservation
     double y2n = y2, y3n = y3;
     if (nHe > 0.0) {
         const double ne1 = xn * nH + (y2 + 2.0 * y3) * nHe;
-        const Tq q2 = make_Tq(iso ? Tiso : Tmun * mu_of(k, xn, y2, y3));
+        const Tq q2 = make_Tq(iso ? cc.Tiso : Tmun * mu_of(k, xn, y2, y3));
         const vd bHe1 = beta_HeI(q2), aHe2 = alphaB_HeII(q2), bHe2 = beta_HeII(q2), aHe3 = alphaB_HeIII(q2);
         const double y1 = 1.0 - y2 - y3;
         const double y1n = (y1 + y2 * aHe2.v * ne1 * h) / (1.0 + (bHe1.v * ne1 + GHeI) * h);
         y2n = (y2 + (y1n * (bHe1.v * ne1 + GHeI) + y3 * aHe3.v * ne1) * h) /
               (1.0 + ((bHe2.v + aHe2.v) * ne1 + GHeII) * h);
         const double ne2 = xn * nH + (y2n + 2.0 * y3) * nHe;
-        const Tq q3 = make_Tq(iso ? Tiso : Tmun * mu_of(k, xn, y2n, y3));
+        const Tq q3 = make_Tq(iso ? cc.Tiso : Tmun * mu_of(k, xn, y2n, y3));
         const vd bHe2b = beta_HeII(q3), aHe3b = alphaB_HeIII(q3);
         y3n = (y3 + y2n * (bHe2b.v * ne2 + GHeII) * h) / (1.0 + aHe3b.v * ne2 * h);
         const double S = y1n + y2n + y3n;
@@ -340,34 +366,31 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, double nH, double T
     }
     // ---- electron density check
     const double nen = xn * nH + (y2n + 2.0 * y3n) * nHe;
-    r = rel_change(nen, ne0);
-    if (r > 0.1) {
+    if (rel_above(nen, ne0, 0.1)) {
         s.h = 0.5 * h;
         return false;
     }
-    maxrel = r > maxrel ? r : maxrel;
+    small &= fabs(nen - ne0) < 0.05 * ne0;
     // ---- accept
 #pragma unroll
     for (int g = 0; g < M; ++g) {
         s.N[g] = Nn[g];
-        s.F[g][0] = Fn[g][0];
-        s.F[g][1] = Fn[g][1];
-        s.F[g][2] = Fn[g][2];
+        s.fs[g] *= rd[g];
     }
     s.x = xn;
     s.y2 = y2n;
     s.y3 = y3n;
-    s.Tmu = iso ? Tiso / mu_of(k, xn, y2n, y3n) : Tmun;
+    s.Tmu = iso ? cc.Tiso / mu_of(k, xn, y2n, y3n) : Tmun;
     s.rem -= h;
     ++s.acc;
-    s.h = maxrel < 0.05 ? 2.0 * h : h;
+    s.h = small ? 2.0 * h : h;
     return !(s.rem > 0.0);
 }
 
 template <int M>
-__device__ __forceinline__ double chem_finish(const KChem &k, double Tiso, const CS &s, unsigned &flags)
+__device__ __forceinline__ double chem_finish(const KChem &k, const CC &cc, const CS &s, unsigned &flags)
 {
-    const double T = k.isothermal ? Tiso : s.Tmu * mu_of(k, s.x, s.y2, s.y3);
+    const double T = k.isothermal ? cc.Tiso : s.Tmu * mu_of(k, s.x, s.y2, s.y3);
 #pragma unroll
     for (int g = 0; g < M; ++g) {
         if (s.N[g] < 0.0) flags |= 8u;
@@ -379,8 +402,8 @@ __device__ __forceinline__ double chem_finish(const KChem &k, double Tiso, const
 
 // Queue of cells still subcycling after the head pass (structure of arrays
 // in caller scratch): the cell index, the attempt counters, and the partial
-// state {N[3], F[3][3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}.
-constexpr int QV = 18;
+// state {N[3], fs[3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}.
+constexpr int QV = 12;
 
 __device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t cell, const CS &s)
 {
@@ -392,15 +415,14 @@ __device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         v[(size_t)g * c] = s.N[g];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[(size_t)(3 + 3 * g + d) * c] = s.F[g][d];
+        v[(size_t)(3 + g) * c] = s.fs[g];
     }
-    v[12 * c] = s.x;
-    v[13 * c] = s.y2;
-    v[14 * c] = s.y3;
-    v[15 * c] = s.Tmu;
-    v[16 * c] = s.rem;
-    v[17 * c] = s.h;
+    v[6 * c] = s.x;
+    v[7 * c] = s.y2;
+    v[8 * c] = s.y3;
+    v[9 * c] = s.Tmu;
+    v[10 * c] = s.rem;
+    v[11 * c] = s.h;
 }
 
 __device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, CS &s)
@@ -412,18 +434,19 @@ __device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, CS &s
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         s.N[g] = v[(size_t)g * c];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) s.F[g][d] = v[(size_t)(3 + 3 * g + d) * c];
+        s.fs[g] = v[(size_t)(3 + g) * c];
     }
-    s.x = v[12 * c];
-    s.y2 = v[13 * c];
-    s.y3 = v[14 * c];
-    s.Tmu = v[15 * c];
-    s.rem = v[16 * c];
-    s.h = v[17 * c];
+    s.x = v[6 * c];
+    s.y2 = v[7 * c];
+    s.y3 = v[8 * c];
+    s.Tmu = v[9 * c];
+    s.rem = v[10 * c];
+    s.h = v[11 * c];
     return (uint32_t)q.cell[p];
 }
 
+// Write a finished cell: N, the flux in the destination scaled by fs, the
+// gas state and the counters.
 template <typename R, int M>
 __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const CS &s, double T)
 {
@@ -432,7 +455,10 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
     for (int g = 0; g < M; ++g) {
         io.N[(size_t)g * nc + i] = (R)s.N[g];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) io.F[(size_t)(3 * g + d) * nc + i] = (R)s.F[g][d];
+        for (int d = 0; d < 3; ++d) {
+            R &f = io.F[(size_t)(3 * g + d) * nc + i];
+            f = (R)((double)f * s.fs[g]);
+        }
     }
     io.xHII[i] = s.x;
     io.xHeII[i] = s.y2;

@@ -10,6 +10,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// All device code of the library is compiled without contraction of
+// multiplies and adds into FMAs (explicit fma() calls, as in the math
+// library, are kept): the compiler's choice of which products to fuse can
+// differ between the kernels that inline the same function, and a cell's
+// result must not depend on the kernel that computes it (first pass or
+// queue, grid or batch, step or tape).  The pragma holds to the end of
+// each translation unit that includes this header.
+#pragma clang fp contract(off)
+
 namespace rtm1 {
 
 constexpr double KB = 1.380649e-16;     // erg/K

@@ -123,13 +123,14 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 // (all groups, source set -> registers); then up to K chemistry attempts.
 // Cells that finish are written to the destination arrays; the rest go to
 // the queue (or, when it is full, finish in place).
-// Waves per SIMD the chemistry kernels are compiled for (caps their VGPRs).
-#ifndef RT_CHEM_WAVES
-#define RT_CHEM_WAVES 1
-#endif
+// Waves per SIMD the head kernel is compiled for: three (168 VGPRs, a few
+// bytes of spill) measured faster than two without spills; the FP64
+// three-group variant spills too much at three and keeps two.
+template <typename R, int M>
+constexpr int head_waves() { return (sizeof(R) == 4 || M < 3) ? 3 : 2; }
 
 template <typename R, int M, int FUSE, int FLUX>
-__global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_head(KGrid g, const KChem *__restrict__ kp, double dt, R c, R kdx, const R *__restrict__ Nin,
+__global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, const KChem *__restrict__ kp, double dt, R c, R kdx, const R *__restrict__ Nin,
                                               const R *__restrict__ Fin, ChemIO<R> io, const R *__restrict__ tab,
                                               int nf, int nth, QueueView q, int K, DevStats *__restrict__ st)
 {
@@ -138,11 +139,19 @@ __global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_head(KGrid g, const KChe
     const bool valid = i < (uint32_t)g.ncell;
     const size_t nc = g.ncell;
     CS s;
-    double nH = 1.0, Tiso = 0.0;
+    CC cc{1.0, 0.0, 0.0, 0.0};
     bool done = true;
     unsigned fl = 0;
+#pragma unroll
+    for (int grp = 0; grp < CM; ++grp) {
+        s.N[grp] = 0.0;
+        s.fs[grp] = 1.0;
+    }
     if (valid) {
+        bool fin = true;
         if (FUSE) {
+            // transport of every group; the flux goes straight to the
+            // destination, where the chemistry rescales it at the end
             int ix, iy, iz;
             cell_coords(g, i, ix, iy, iz);
             const Nbr nb = neighbours(g, i, ix, iy, iz);
@@ -151,26 +160,26 @@ __global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_head(KGrid g, const KChe
                 const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc,
                                                         Fin + (size_t)3 * grp * nc, c, kdx, tab, nf, nth);
                 s.N[grp] = (double)o.n;
-                s.F[grp][0] = (double)o.fx;
-                s.F[grp][1] = (double)o.fy;
-                s.F[grp][2] = (double)o.fz;
+                io.F[(size_t)(3 * grp) * nc + i] = o.fx;
+                io.F[(size_t)(3 * grp + 1) * nc + i] = o.fy;
+                io.F[(size_t)(3 * grp + 2) * nc + i] = o.fz;
+                fin = fin && isfinite(o.fx) && isfinite(o.fy) && isfinite(o.fz);
             }
         } else {
 #pragma unroll
             for (int grp = 0; grp < M; ++grp) {
                 s.N[grp] = (double)io.N[(size_t)grp * nc + i];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) s.F[grp][d] = (double)io.F[(size_t)(3 * grp + d) * nc + i];
+                for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.F[(size_t)(3 * grp + d) * nc + i]);
             }
         }
         s.x = io.xHII[i];
         s.y2 = io.xHeII[i];
         s.y3 = io.xHeIII[i];
-        Tiso = io.T[i];
-        nH = io.nH[i];
-        if (chem_init<M>(k, dt, Tiso, s)) {
+        cc = make_cc(k, io.nH[i], io.T[i]);
+        if (chem_init<CM>(k, dt, cc.Tiso, fin, s)) {
             done = false;
-            for (int a = 0; a < K && !done; ++a) done = chem_attempt<M>(k, nH, Tiso, s, fl);
+            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM>(k, cc, s, fl);
         } else {
             fl |= 2u;
         }
@@ -193,11 +202,11 @@ __global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_head(KGrid g, const KChe
         }
     }
     if (want && !queued) {
-        while (!done) done = chem_attempt<M>(k, nH, Tiso, s, fl);
+        while (!done) done = chem_attempt<CM>(k, cc, s, fl);
     }
     unsigned long long a_acc = 0, a_att = 0;
     if (valid && !queued) {
-        const double T = chem_finish<M>(k, Tiso, s, fl);
+        const double T = chem_finish<CM>(k, cc, s, fl);
         store_cell<R, M>(io, i, s, T);
         a_acc = (unsigned long long)s.acc;
         a_att = (unsigned long long)s.att;
@@ -210,13 +219,13 @@ __global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_head(KGrid g, const KChe
 // their cell has filled dt_RT, so that a few slow cells do not hold whole
 // waves of finished lanes.
 template <typename R, int M>
-__global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
+__global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
     const unsigned n = min(*q.count, q.cap);
     CS s;
     uint32_t cell = 0;
-    double nH = 1.0, Tiso = 0.0;
+    CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
     unsigned fl = 0;
     unsigned long long a_acc = 0, a_att = 0, a_max = 0;
@@ -234,8 +243,7 @@ __global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_tail(const KChem *__rest
                     const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
                     if (p < n) {
                         cell = q_load(q, p, s);
-                        nH = io.nH[cell];
-                        Tiso = io.T[cell];
+                        cc = make_cc(k, io.nH[cell], io.T[cell]);
                         active = true;
                     }
                 }
@@ -243,8 +251,8 @@ __global__ __launch_bounds__(256, RT_CHEM_WAVES) void k_tail(const KChem *__rest
         }
         if (!__any(active)) break;
         if (active) {
-            if (chem_attempt<M>(k, nH, Tiso, s, fl)) {
-                const double T = chem_finish<M>(k, Tiso, s, fl);
+            if (chem_attempt<CM>(k, cc, s, fl)) {
+                const double T = chem_finish<CM>(k, cc, s, fl);
                 store_cell<R, M>(io, cell, s, T);
                 a_acc += (unsigned long long)s.acc;
                 a_att += (unsigned long long)s.att;

@@ -62,21 +62,34 @@ def test_256_cubed_sampled_cells_match_oracle(fp32):
     # 1/(1 + h c sigma n_HI) of every substep differ by ~1e-16/x_HI relative;
     # over the step's optical depth (<~ 100) N and F pick up ~1e-14/x_HI.
     xhi = np.maximum(1.0 - r["x"][:, 0], 1e-6)
+    # max of the injected pre-step N over each sampled cell's periodic stencil
+    nx, ny, nz = w.n
+    ix, iy, iz = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+    nstencil = []
+    for gi in range(M):
+        Ng = pre["N"][gi]
+        m = Ng[iz, iy, ix].copy()
+        for dz, dy, dx_ in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            m = np.maximum(m, Ng[(iz + dz) % nz, (iy + dy) % ny, (ix + dx_) % nx])
+        nstencil.append(m)
     rtol = tol + 1e-14 / xhi
     for gi in range(M):
         sc = np.max(np.abs(r["N"][:, gi]))
         err = np.abs(gN[same, gi] - r["N"][same, gi])
         lim = rtol[same] * np.abs(r["N"][same, gi]) + tol * 1e-3 * sc
-        w = np.argmax(err / lim)
-        print(f"N{gi}: worst err/limit {err[w] / lim[w]:.3g} (x_HI {xhi[same][w]:.3g})", flush=True)
+        iw = np.argmax(np.where(lim > 0, err / np.where(lim > 0, lim, 1.0), 0.0))
+        print(f"N{gi}: worst err/limit {err[iw] / lim[iw]:.3g} (x_HI {xhi[same][iw]:.3g})", flush=True)
         assert np.all(err <= lim), (gi, err.max())
-        # flux components are compared on the scale of the cell's |F|
+        # F on the scale of the local radiation: the transport update adds
+        # terms of order c_r N of the stencil, so |F| << c_r N comes out of
+        # a cancellation; the error is bounded relative to |F| and, as a
+        # reduced-flux error, relative to c_r max(N over the 7-point stencil)
         Fn = np.linalg.norm(r["F"][same, gi], axis=1)
-        scF = np.max(np.linalg.norm(r["F"][:, gi], axis=1))
         errF = np.linalg.norm(gF[same, gi] - r["F"][same, gi], axis=1)
-        limF = rtol[same] * Fn + tol * 1e-3 * scF
-        w = np.argmax(errF / limF)
-        print(f"F{gi}: worst err/limit {errF[w] / limF[w]:.3g} (|F| {Fn[w]:.3g}, x_HI {xhi[same][w]:.3g})", flush=True)
+        limF = rtol[same] * Fn + tol * w.c_r * nstencil[gi][same]
+        iw = np.argmax(np.where(limF > 0, errF / np.where(limF > 0, limF, 1.0), 0.0))
+        print(f"F{gi}: worst err/limit {errF[iw] / limF[iw]:.3g} (|F| {Fn[iw]:.3g}, c_r N_stencil "
+              f"{w.c_r * nstencil[gi][same][iw]:.3g}, x_HI {xhi[same][iw]:.3g})", flush=True)
         assert np.all(errF <= limF), (gi, errF.max())
     for q in range(3):
         err = np.abs(gx[same, q] - r["x"][same, q])
