@@ -374,6 +374,7 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     k.x_min = params->x_min;
     k.N_floor = params->N_floor;
     k.max_att = params->max_attempts;
+    kchem_derive(k);
 
     build_hll(c->nf, c->nth, c->hll_host);
     hipError_t e;

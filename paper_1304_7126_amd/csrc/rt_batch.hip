@@ -501,6 +501,7 @@ extern "C" rt_status rt_batch_init(int nbox, const rt_grid *grids, const rt_grou
         k.x_min = params->x_min;
         k.N_floor = params->N_floor;
         k.max_att = params->max_attempts;
+        kchem_derive(k);
     }
     // chunk order: largest boxes (cells x groups) first, cells in order
     std::vector<int> order(nbox);

@@ -262,7 +262,7 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s
     bool fail = false;
 #pragma unroll
     for (int g = 0; g < M; ++g) {
-        const double D = k.cr * (k.sN[g][0] * nHI + k.sN[g][1] * nHeI + k.sN[g][2] * nHeII);
+        const double D = k.csN[g][0] * nHI + k.csN[g][1] * nHeI + k.csN[g][2] * nHeII;
         rd[g] = 1.0 / (1.0 + h * D);
         Nn[g] = s.N[g] * rd[g];
         if (s.N[g] > k.N_floor) {
@@ -283,12 +283,11 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s
         double H = 0.0;
         {
             const double nj[3] = {nHI, nHeI, nHeII};
-            const double ej[3] = {EPS_HI, EPS_HEI, EPS_HEII};
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 double sj = 0.0;
 #pragma unroll
-                for (int g = 0; g < M; ++g) sj += k.cr * Nn[g] * (k.eb[g] * k.sE[g][j] - ej[j] * k.sN[g][j]);
+                for (int g = 0; g < M; ++g) sj += Nn[g] * k.hc[g][j];
                 H += nj[j] * sj;
             }
         }
@@ -312,9 +311,9 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s
     double GHI = 0.0, GHeI = 0.0, GHeII = 0.0;
 #pragma unroll
     for (int g = 0; g < M; ++g) {
-        GHI += k.sN[g][0] * k.cr * Nn[g];
-        GHeI += k.sN[g][1] * k.cr * Nn[g];
-        GHeII += k.sN[g][2] * k.cr * Nn[g];
+        GHI += k.csN[g][0] * Nn[g];
+        GHeI += k.csN[g][1] * Nn[g];
+        GHeII += k.csN[g][2] * Nn[g];
     }
     const Tq q1 = make_Tq(iso ? cc.Tiso : Tmun * mu0);
     const vd bH = beta_HI(q1);

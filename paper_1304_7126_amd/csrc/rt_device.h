@@ -220,7 +220,15 @@ __device__ __forceinline__ vd alphaB_HeIII(const Tq &q)
     return r_hg(q, 5.506e-14, LN_TL_HEII, 1.5, LN_2p74, 0.407, 2.242);
 }
 
+// (lambda_HeII / lambda_HI)^0.376 = (1263030 / 315614)^0.376: the ratio of
+// the Hui & Gnedin terms (lambda/2.25)^0.376 of the HeIII and HII
+// recombination-cooling fits at one temperature
+constexpr double HG_COOL_U_RATIO = 1.6844137772424854;
+
 // Primordial cooling L of eq. (rate_cooling), case B (OTSA), and dL/dT.
+// Products of exponentials are taken as one exponential of the summed
+// arguments, and the HeIII recombination term reuses the HII term's
+// (lambda/l0)^q.
 __device__ __forceinline__ void cooling_B(const Tq &q, double a_exp, double ne, double nHI, double nHII,
                                           double nHeI, double nHeII, double nHeIII, double &L, double &dL)
 {
@@ -237,16 +245,26 @@ __device__ __forceinline__ void cooling_B(const Tq &q, double a_exp, double ne, 
     // collisional excitation
     const double gdl = -0.5 * q.s5 * q.g;
     const double psHI = 7.5e-19 * q.g * exp(-118348.0 * q.invT), psHIl = gdl + 118348.0 * q.invT;
-    const double psHeII = 5.54e-17 * exp(-0.397 * q.lnT) * q.g * exp(-473638.0 * q.invT);
+    const double psHeII = 5.54e-17 * q.g * exp(-0.397 * q.lnT - 473638.0 * q.invT);
     const double psHeIIl = -0.397 + gdl + 473638.0 * q.invT;
-    // recombination cooling, case B
-    const vd eHII = r_hgc(q, 3.435e-30, LN_TL_HI, 1.97, LN_2p25, 0.376, 3.72);
+    // recombination cooling, case B: B T lam^p / (1 + (lam/l0)^q)^r for HII
+    // (lam = 315614/T) and HeIII (lam = 1263030/T, 8 B)
+    vd eHII, eHeIII;
+    {
+        constexpr double p = 1.97, qq = 0.376, r = 3.72;
+        const double l1 = LN_TL_HI - q.lnT, l3 = LN_TL_HEII - q.lnT;
+        const double u1 = exp(qq * (l1 - LN_2p25));
+        const double u3 = u1 * HG_COOL_U_RATIO;
+        eHII.v = 3.435e-30 * q.T * exp(p * l1 - r * log1p(u1));
+        eHeIII.v = 8.0 * 3.435e-30 * q.T * exp(p * l3 - r * log1p(u3));
+        eHII.d = eHII.v * (1.0 - (p - r * qq * u1 / (1.0 + u1))) * q.invT;
+        eHeIII.d = eHeIII.v * (1.0 - (p - r * qq * u3 / (1.0 + u3))) * q.invT;
+    }
     const vd aB2 = r_pw(q, 1.26e-14, LN_TL_HEI, 0.75);
     const double eHeII = KB * q.T * aB2.v, eHeIIl = 1.0 - 0.75;
-    const vd eHeIII = r_hgc(q, 8.0 * 3.435e-30, LN_TL_HEII, 1.97, LN_2p25, 0.376, 3.72);
     // dielectronic recombination
-    const double ed1 = exp(-470000.0 * q.invT), ed2 = exp(-94000.0 * q.invT);
-    const double om = 1.24e-13 * exp(-1.5 * q.lnT) * ed1 * (1.0 + 0.3 * ed2);
+    const double ed2 = exp(-94000.0 * q.invT);
+    const double om = 1.24e-13 * exp(-1.5 * q.lnT - 470000.0 * q.invT) * (1.0 + 0.3 * ed2);
     const double oml = -1.5 + 470000.0 * q.invT + 0.3 * ed2 * 94000.0 * q.invT / (1.0 + 0.3 * ed2);
     // bremsstrahlung and Compton
     const double th = 1.42e-27 * sqT;

@@ -22,6 +22,8 @@ struct KChem {
     double sN[3][3];
     double sE[3][3];
     double eb[3];
+    double csN[3][3];  // c_r sigN[g][j]: absorption and photoionisation rate per photon
+    double hc[3][3];   // c_r (ebar_g sigE[g][j] - eps_j sigN[g][j]): photoheating per photon
     double X, Y;
     double Kfac;   // (gamma-1) X / k_B ; K = Kfac / n_H
     double a_exp;
@@ -98,6 +100,19 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,
                          hipStream_t s);
+
+// ionisation energies of HI, HeI, HeII [erg] (App. E.4)
+constexpr double EPS_ION_ERG[3] = {13.60 * 1.602176634e-12, 24.59 * 1.602176634e-12, 54.42 * 1.602176634e-12};
+
+// fill the derived per-photon rates csN, hc from cr, sN, sE, eb
+inline void kchem_derive(KChem &k)
+{
+    for (int g = 0; g < 3; ++g)
+        for (int j = 0; j < 3; ++j) {
+            k.csN[g][j] = k.sN[g][j] * k.cr;
+            k.hc[g][j] = k.cr * (k.eb[g] * k.sE[g][j] - EPS_ION_ERG[j] * k.sN[g][j]);
+        }
+}
 
 // differentiation form (rt_adjoint.hip)
 size_t adj_scan_parts(size_t nc);
