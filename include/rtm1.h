@@ -145,6 +145,17 @@ typedef struct {
     long long attempts_total; /* chemistry attempts (accepted + restarted)          */
     long long attempts_max;   /* largest per-cell attempt count in one step         */
     unsigned flags;           /* RT_FLAG_* bits                                     */
+    /* photon accounting, filled while rt_set_accounting is on (zero otherwise):
+     * per group, photons injected by the sources, absorbed by the chemistry
+     * (totals entering minus leaving each chemistry pass) and carried out of
+     * the grid through outflow or reflecting faces by the transport; with
+     * photons(t) = photons(t0) + injected - absorbed - outflow as the budget
+     * (Sec. 3 operator split).  substep_hist[k] counts cell-steps with k
+     * accepted chemistry substeps (k = 63: 63 or more). */
+    double injected[3];
+    double absorbed[3];
+    double outflow[3];
+    long long substep_hist[64];
 } rt_stats;
 
 typedef struct rt_ctx rt_ctx;
@@ -204,6 +215,14 @@ rt_status rt_set_tuning(rt_ctx *ctx, int head_attempts, long long queue_cap);
  * the stream.  Needs a bound scratch buffer. */
 rt_status rt_get_stats(rt_ctx *ctx, rt_stats *out);
 rt_status rt_reset_stats(rt_ctx *ctx);
+
+/* Photon accounting on (1) or off (0, the default) for rt_step,
+ * rt_transport and rt_thermochem.  While on, every step also sums the
+ * transported photons and the boundary outflow per block, runs a
+ * fixed-order reduction of the photon totals after its chemistry and
+ * histograms the substeps (a few percent of extra work); the sums are
+ * reproducible run to run.  The batched form does not account. */
+rt_status rt_set_accounting(rt_ctx *ctx, int enabled);
 
 /* Photon-group attributes of a blackbody source at temperature T_bb [K]
  * for M groups bounded by edges_eV[0..M] (edges_eV[M] may be +inf):

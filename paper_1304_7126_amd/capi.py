@@ -25,7 +25,7 @@ EXPORTED = [
     "rt_batch_init", "rt_batch_scratch_bytes", "rt_batch_bind", "rt_batch_set_stream", "rt_batch_current",
     "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
-    "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint",
+    "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint", "rt_set_accounting",
 ]
 
 
@@ -59,7 +59,9 @@ class RtStats(ctypes.Structure):
     _fields_ = [("photons", ctypes.c_double * 3), ("ionised_H", ctypes.c_double),
                 ("max_f", ctypes.c_double), ("min_N", ctypes.c_double),
                 ("substeps_total", ctypes.c_longlong), ("attempts_total", ctypes.c_longlong),
-                ("attempts_max", ctypes.c_longlong), ("flags", ctypes.c_uint)]
+                ("attempts_max", ctypes.c_longlong), ("flags", ctypes.c_uint),
+                ("injected", ctypes.c_double * 3), ("absorbed", ctypes.c_double * 3),
+                ("outflow", ctypes.c_double * 3), ("substep_hist", ctypes.c_longlong * 64)]
 
 
 class RtTiming(ctypes.Structure):
@@ -126,6 +128,8 @@ def lib():
     L.rt_get_stats.restype = st
     L.rt_reset_stats.argtypes = [vp]
     L.rt_reset_stats.restype = st
+    L.rt_set_accounting.argtypes = [vp, ctypes.c_int]
+    L.rt_set_accounting.restype = st
     L.rt_group_attributes.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp]
     L.rt_group_attributes.restype = st
     L.rt_hll_table.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int),

@@ -39,6 +39,11 @@ struct rt_ctx {
     unsigned qcap = 0;               // chemistry queue capacity (cells)
     unsigned qcap_max = 0;           // capacity the scratch size is computed for
     int head_attempts = HEAD_ATTEMPTS;
+    // photon accounting
+    bool acct = false;
+    bool acct_pending = false;       // transport partials of the current step
+    double injected[3] = {0, 0, 0};  // photons injected since the last reset (host sum)
+    std::vector<double> src_rate_host;
     // kernel timing
     bool timing = false;
     struct Pend {
@@ -413,7 +418,14 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
 
 static size_t scratch_need(const rt_ctx *c)
 {
-    return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max);
+    return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max) + acct_bytes(c->grid.ncell);
+}
+
+// accounting partials: after the reduction partials and the queue
+static double *acct_part(const rt_ctx *c)
+{
+    return (double *)((char *)c->st.scratch + ((reduction_scratch_bytes() + 255) & ~(size_t)255) +
+                      queue_bytes(c->qcap_max));
 }
 
 extern "C" size_t rt_scratch_bytes(const rt_ctx *c)
@@ -487,6 +499,7 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     if (c->src_in_rate) { (void)hipFree(c->src_in_rate); c->src_in_rate = nullptr; }
     c->nsrc = 0;
     c->nsrc_in = 0;
+    c->src_rate_host.clear();
     if (cells.empty()) return RT_OK;
     {
         std::vector<int32_t> in_cell(n);
@@ -507,6 +520,7 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     RT_HIP(c, hipMemcpy(c->src_cell, cells.data(), cells.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     RT_HIP(c, hipMemcpy(c->src_rate, rates.data(), rates.size() * sizeof(double), hipMemcpyHostToDevice));
     c->nsrc = (int)cells.size();
+    c->src_rate_host = rates;
     return RT_OK;
 }
 
@@ -539,6 +553,9 @@ static rt_status do_inject(rt_ctx *c, double dt)
 {
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
     if (c->nsrc == 0) return RT_OK;
+    if (c->acct)
+        for (int q = 0; q < c->nsrc; ++q)
+            for (int g = 0; g < c->groups.M; ++g) c->injected[g] += c->src_rate_host[(size_t)q * c->groups.M + g] * dt;
     return timed(c, TM_INJECT, [&]() -> rt_status {
         RT_HIP(c, launch_inject(c->fp32, c->st.N[c->cur], c->grid.ncell, c->groups.M, c->nsrc, c->src_cell,
                                 c->src_rate, dt / V, c->stream));
@@ -553,27 +570,57 @@ static rt_status do_transport(rt_ctx *c, double dt)
     const int s = c->cur, d = 1 - c->cur;
     rt_status r = timed(c, TM_TRANSPORT, [&]() -> rt_status {
         RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, c->groups.c_r, dt, c->st.N[s],
-                                   c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth, c->stream));
+                                   c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth,
+                                   c->acct ? acct_part(c) : nullptr, c->stream));
         return RT_OK;
     });
     if (r != RT_OK) return r;
     c->cur = d;
+    c->acct_pending = c->acct;
+    return RT_OK;
+}
+
+// photon totals of the current radiation set into dred
+static rt_status acct_reduce(rt_ctx *c)
+{
+    const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+    RT_HIP(c, launch_reduce(c->fp32, c->grid.ncell, c->groups.M, c->groups.c_r, V, c->st.N[c->cur], c->st.F[c->cur],
+                            c->st.xHII, c->st.nH, c->st.scratch, c->dred, c->stream));
+    return RT_OK;
+}
+
+// close the step's ledger after the chemistry
+static rt_status acct_close(rt_ctx *c, double dt)
+{
+    const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+    rt_status r = acct_reduce(c);
+    if (r != RT_OK) return r;
+    RT_HIP(c, launch_ledger(c->acct_pending ? 2 : 1, acct_part(c), acct_blocks(c->grid.ncell), c->groups.M, V,
+                            dt * c->grid.dx * c->grid.dx, c->dred, c->dstats, c->stream));
+    c->acct_pending = false;
     return RT_OK;
 }
 
 static rt_status do_chem(rt_ctx *c, double dt)
 {
     const QueueView q = queue_view(c->st.scratch, c->qcap, c->qcap_max);
+    if (c->acct && !c->acct_pending) {
+        // no transport before this chemistry: its input totals come from a reduction
+        rt_status r = acct_reduce(c);
+        if (r != RT_OK) return r;
+        RT_HIP(c, launch_ledger(0, nullptr, 0, c->groups.M, 0.0, 0.0, c->dred, c->dstats, c->stream));
+    }
+    unsigned long long *hist = c->acct ? c->dstats->hist : nullptr;
     for (int part = 1; part <= 2; ++part) {
         rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
             RT_HIP(c, launch_chem(part, c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
                                   c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, q,
-                                  c->head_attempts, c->dstats, c->stream));
+                                  c->head_attempts, hist, c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
     }
-    return RT_OK;
+    return c->acct ? acct_close(c, dt) : RT_OK;
 }
 
 // transport and thermochemistry in one pass over the grid (source set ->
@@ -589,13 +636,16 @@ static rt_status do_fused(rt_ctx *c, double dt)
             RT_HIP(c, launch_step_fused(part, c->fp32, c->params.flux, c->grid, c->kchem, c->dkchem, dt, c->st.N[s], c->st.F[s],
                                         c->st.N[d], c->st.F[d], c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T,
                                         c->st.nH, c->st.nacc, c->st.natt, c->hll_dev, c->nf, c->nth, q,
-                                        c->head_attempts, c->dstats, c->stream));
+                                        c->head_attempts, c->acct ? acct_part(c) : nullptr,
+                                        c->acct ? c->dstats->hist : nullptr, c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
     }
     c->cur = d;
-    return RT_OK;
+    if (!c->acct) return RT_OK;
+    c->acct_pending = true;
+    return acct_close(c, dt);
 }
 
 extern "C" rt_status rt_inject(rt_ctx *c, double dt)
@@ -656,6 +706,12 @@ extern "C" rt_status rt_get_stats(rt_ctx *c, rt_stats *out)
     out->attempts_total = (long long)d.att_total;
     out->attempts_max = (long long)d.att_max;
     out->flags = d.flags;
+    for (int g = 0; g < 3; ++g) {
+        out->injected[g] = c->injected[g];
+        out->absorbed[g] = d.absorbed[g];
+        out->outflow[g] = d.outflow[g];
+    }
+    for (int b = 0; b < 64; ++b) out->substep_hist[b] = (long long)d.hist[b];
     return RT_OK;
 }
 
@@ -663,6 +719,15 @@ extern "C" rt_status rt_reset_stats(rt_ctx *c)
 {
     if (!c) return RT_EINVAL;
     RT_HIP(c, hipMemsetAsync(c->dstats, 0, sizeof(DevStats), c->stream));
+    for (int g = 0; g < 3; ++g) c->injected[g] = 0.0;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_accounting(rt_ctx *c, int enabled)
+{
+    if (!c) return RT_EINVAL;
+    c->acct = enabled != 0;
+    c->acct_pending = false;
     return RT_OK;
 }
 
@@ -731,6 +796,15 @@ static rt_status tape_ok(rt_ctx *c, const rt_tape *t)
     return RT_OK;
 }
 
+// the photon accounting covers rt_step, rt_transport and rt_thermochem: it
+// is paused while a step is recorded or replayed
+struct AcctPause {
+    rt_ctx *c;
+    bool was;
+    explicit AcctPause(rt_ctx *ctx) : c(ctx), was(ctx->acct) { c->acct = false; }
+    ~AcctPause() { c->acct = was; }
+};
+
 extern "C" size_t rt_tape_offsets_len(const rt_ctx *c)
 {
     if (!c) return 0;
@@ -743,6 +817,7 @@ extern "C" rt_status rt_step_record(rt_ctx *c, double dt, const rt_tape *t)
     rt_status r = adj_supported(c, dt);
     if (r != RT_OK) return r;
     if ((r = tape_ok(c, t)) != RT_OK) return r;
+    AcctPause pause(c);
     const size_t nc = c->grid.ncell;
     RT_HIP(c, launch_offsets(t->counts, nc, t->off, c->stream));
     if ((r = do_inject(c, dt)) != RT_OK) return r;
@@ -763,6 +838,7 @@ extern "C" rt_status rt_step_replay(rt_ctx *c, double dt, const rt_tape *t)
     rt_status r = adj_supported(c, dt);
     if (r != RT_OK) return r;
     if ((r = tape_ok(c, t)) != RT_OK) return r;
+    AcctPause pause(c);
     const size_t nc = c->grid.ncell;
     if ((r = do_inject(c, dt)) != RT_OK) return r;
     if ((r = do_transport(c, dt)) != RT_OK) return r;

@@ -36,7 +36,8 @@ __device__ __forceinline__ R comp(const U4<R> &u, int d)
 // reflect repeats it with the normal flux component negated (bit d of refl).
 struct Nbr {
     uint32_t idx[6];
-    unsigned refl;
+    unsigned refl;   // bit f: face f's ghost mirrors the normal flux
+    unsigned ghost;  // bit f: face f is a boundary face (outflow or reflect)
 };
 
 __device__ __forceinline__ void cell_coords(const KGrid &g, uint32_t i, int &ix, int &iy, int &iz)
@@ -52,6 +53,7 @@ __device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, in
 {
     Nbr nb;
     nb.refl = 0;
+    nb.ghost = 0;
     const int c[3] = {ix, iy, iz};
     const int n[3] = {g.nx, g.ny, g.nz};
     const uint32_t stride[3] = {1u, (uint32_t)g.nx, (uint32_t)g.nx * (uint32_t)g.ny};
@@ -64,6 +66,7 @@ __device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, in
             nb.idx[2 * d] = i + stride[d] * (uint32_t)(n[d] - 1);
         } else {
             nb.idx[2 * d] = i;
+            nb.ghost |= 1u << (2 * d);
             if (g.bc[2 * d] == 2) nb.refl |= 1u << (2 * d);
         }
         // high side
@@ -73,6 +76,7 @@ __device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, in
             nb.idx[2 * d + 1] = i - stride[d] * (uint32_t)(n[d] - 1);
         } else {
             nb.idx[2 * d + 1] = i;
+            nb.ghost |= 1u << (2 * d + 1);
             if (g.bc[2 * d + 1] == 2) nb.refl |= 1u << (2 * d + 1);
         }
     }
@@ -125,10 +129,12 @@ __device__ __forceinline__ void face_flux(const U4<R> &L, const R PL[6], R lLm, 
 // Transport of one group of one cell: every face flux from the source
 // arrays (N, F of this group),
 //   U' = U + dt/dx * sum_d (Phi_{d,-1/2} - Phi_{d,+1/2})     (eq. dUdt_sol)
+// bout receives the photon-density flux out of the grid through the cell's
+// boundary faces (high faces count +Phi_N, low faces -Phi_N).
 template <typename R, int FLUX>
 __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_t nc, const R *__restrict__ N,
                                                 const R *__restrict__ F, R c, R kdx, const R *__restrict__ tab,
-                                                int nf, int nth)
+                                                int nf, int nth, double &bout)
 {
     const U4<R> C = load_u(N, F, nc, i);
     R PC[6];
@@ -161,6 +167,8 @@ __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_
         face_flux<R, FLUX>(C, PC, lCm, lCp, Rt, PR, lRm, lRp, d, c, Pp);
 #pragma unroll
         for (int m = 0; m < 4; ++m) acc[m] += Pm[m] - Pp[m];
+        if (nb.ghost & (1u << (2 * d))) bout -= (double)Pm[0];
+        if (nb.ghost & (1u << (2 * d + 1))) bout += (double)Pp[0];
     }
     U4<R> o;
     o.n = C.n + kdx * acc[0];

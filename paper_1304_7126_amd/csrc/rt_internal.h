@@ -39,6 +39,11 @@ struct DevStats {
     unsigned long long att_max;
     unsigned int flags;
     unsigned int pad;
+    // photon accounting (rt_set_accounting): photons absorbed by the
+    // chemistry and carried out through boundary faces, per group; the
+    // pre-chemistry total of a step; histogram of accepted substeps per cell
+    double absorbed[3], outflow[3], Tpre[3];
+    unsigned long long hist[64];
 };
 
 // final reduction record (in caller scratch)
@@ -56,9 +61,22 @@ size_t reduction_scratch_bytes();
 hipError_t launch_inject(bool fp32, void *N, size_t ncell, int M, int nsrc, const int32_t *cell,
                          const double *rate, double dt_over_V, hipStream_t s);
 
+// accounting partials: 6 doubles per transport block (sum of transported N
+// and of the outward boundary flux, per group), in caller scratch
+constexpr int ACCT_THREADS = 256;
+size_t acct_bytes(size_t ncell);
+unsigned acct_blocks(size_t ncell);
+
 hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c, double dt,
                             const void *Nin, const void *Fin, void *Nout, void *Fout, const void *hll,
-                            int nf, int nth, hipStream_t s);
+                            int nf, int nth, double *acct, hipStream_t s);
+
+// mode 0: record the current photon totals as the pre-chemistry totals;
+// mode 1: absorbed += pre-chemistry totals - current totals;
+// mode 2: as 1 with the pre-chemistry totals and the outflow taken from the
+// transport partials.  red holds the current totals (launch_reduce).
+hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, int M, double V, double dtdx2,
+                         const RedOut *red, DevStats *st, hipStream_t s);
 
 // queue of cells still subcycling after the head pass (caller scratch)
 struct QueueView {
@@ -77,6 +95,8 @@ struct ChemIO {
     double *xHII, *xHeII, *xHeIII, *T;
     const double *nH;
     int32_t *nacc, *natt;
+    double *acct;               // transport partials (fused head), or null
+    unsigned long long *hist;   // substep histogram, or null
 };
 
 constexpr int TAIL_BLOCKS = 1024;
@@ -90,12 +110,13 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
 // part 1: queue reset + head pass; part 2: tail pass
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
-                       const QueueView &q, int K, DevStats *stats, hipStream_t s);
+                       const QueueView &q, int K, unsigned long long *hist, DevStats *stats, hipStream_t s);
 
 hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, const KChem &kc, const KChem *dk, double dt, const void *Nin,
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
-                             int nth, const QueueView &q, int K, DevStats *stats, hipStream_t s);
+                             int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
+                             DevStats *stats, hipStream_t s);
 
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,

@@ -42,44 +42,76 @@ hipError_t launch_inject(bool fp32, void *N, size_t ncell, int M, int nsrc, cons
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------- accounting
+unsigned acct_blocks(size_t ncell) { return (unsigned)((ncell + ACCT_THREADS - 1) / ACCT_THREADS); }
+size_t acct_bytes(size_t ncell) { return ((size_t)acct_blocks(ncell) * 6 * sizeof(double) + 255) & ~(size_t)255; }
+
+// Fixed-order block sum of the per-thread values v[0..5] (transported N and
+// outward boundary flux per group) into part[6 * blockIdx.x + q].  Called by
+// every thread of a 256-thread block.
+__device__ __forceinline__ void block_acct(double *part, const double v[6])
+{
+    __shared__ double sh[6][ACCT_THREADS];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sh[q][t] = v[q];
+    __syncthreads();
+    for (int o = ACCT_THREADS / 2; o > 0; o >>= 1) {
+        if (t < o) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sh[q][t] += sh[q][t + o];
+        }
+        __syncthreads();
+    }
+    if (t < 6) part[(size_t)6 * blockIdx.x + t] = sh[t][0];
+}
+
 // --------------------------------------------------------------- transport
 template <typename R, int FLUX>
 __global__ __launch_bounds__(256) void k_transport(KGrid g, int M, R c, R kdx, const R *__restrict__ Nin,
                                                    const R *__restrict__ Fin, R *__restrict__ Nout,
                                                    R *__restrict__ Fout, const R *__restrict__ tab, int nf,
-                                                   int nth)
+                                                   int nth, double *__restrict__ acct)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (uint32_t)g.ncell) return;
     const size_t nc = g.ncell;
-    int ix, iy, iz;
-    cell_coords(g, i, ix, iy, iz);
-    const Nbr nb = neighbours(g, i, ix, iy, iz);
-    for (int grp = 0; grp < M; ++grp) {
-        const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc, Fin + (size_t)3 * grp * nc, c,
-                                                kdx, tab, nf, nth);
-        Nout[(size_t)grp * nc + i] = o.n;
-        R *Fo = Fout + (size_t)3 * grp * nc;
-        Fo[i] = o.fx;
-        Fo[nc + i] = o.fy;
-        Fo[2 * nc + i] = o.fz;
+    double av[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < (uint32_t)nc) {
+        int ix, iy, iz;
+        cell_coords(g, i, ix, iy, iz);
+        const Nbr nb = neighbours(g, i, ix, iy, iz);
+        for (int grp = 0; grp < M; ++grp) {
+            double bout = 0.0;
+            const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc, Fin + (size_t)3 * grp * nc,
+                                                    c, kdx, tab, nf, nth, bout);
+            Nout[(size_t)grp * nc + i] = o.n;
+            R *Fo = Fout + (size_t)3 * grp * nc;
+            Fo[i] = o.fx;
+            Fo[nc + i] = o.fy;
+            Fo[2 * nc + i] = o.fz;
+            if (grp < 3) {
+                av[grp] = (double)o.n;
+                av[3 + grp] = bout;
+            }
+        }
     }
+    if (acct) block_acct(acct, av);
 }
 
 hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c, double dt, const void *Nin,
                             const void *Fin, void *Nout, void *Fout, const void *hll, int nf, int nth,
-                            hipStream_t s)
+                            double *acct, hipStream_t s)
 {
     dim3 b(256), gr((unsigned)((g.ncell + 255) / 256));
     const double k = dt / g.dx;
     if (fp32) {
         auto kern = flux ? k_transport<float, 1> : k_transport<float, 0>;
         hipLaunchKernelGGL(kern, gr, b, 0, s, g, M, (float)c, (float)k, (const float *)Nin, (const float *)Fin,
-                           (float *)Nout, (float *)Fout, (const float *)hll, nf, nth);
+                           (float *)Nout, (float *)Fout, (const float *)hll, nf, nth, acct);
     } else {
         auto kern = flux ? k_transport<double, 1> : k_transport<double, 0>;
         hipLaunchKernelGGL(kern, gr, b, 0, s, g, M, c, k, (const double *)Nin, (const double *)Fin,
-                           (double *)Nout, (double *)Fout, (const double *)hll, nf, nth);
+                           (double *)Nout, (double *)Fout, (const double *)hll, nf, nth, acct);
     }
     return hipGetLastError();
 }
@@ -119,6 +151,20 @@ __device__ __forceinline__ void block_stats(DevStats *st, unsigned long long acc
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
+// Histogram of accepted substeps per cell (bin 63: 63 or more), counted in
+// LDS per block and added to the device statistics at the end of the block.
+__device__ __forceinline__ void hist_init(unsigned *sh)
+{
+    if (threadIdx.x < 64) sh[threadIdx.x] = 0u;
+    __syncthreads();
+}
+__device__ __forceinline__ void hist_add(unsigned *sh, int acc) { atomicAdd(&sh[acc < 63 ? acc : 63], 1u); }
+__device__ __forceinline__ void hist_flush(const unsigned *sh, unsigned long long *hist)
+{
+    __syncthreads();
+    if (threadIdx.x < 64 && sh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)sh[threadIdx.x]);
+}
+
 // Head pass: one thread per cell.  With FUSE the cell is first transported
 // (all groups, source set -> registers); then up to K chemistry attempts.
 // Cells that finish are written to the destination arrays; the rest go to
@@ -142,6 +188,9 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool done = true;
     unsigned fl = 0;
+    double av[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    __shared__ unsigned s_hist[64];
+    if (io.hist) hist_init(s_hist);
 #pragma unroll
     for (int grp = 0; grp < CM; ++grp) {
         s.N[grp] = 0.0;
@@ -157,9 +206,12 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
             const Nbr nb = neighbours(g, i, ix, iy, iz);
 #pragma unroll
             for (int grp = 0; grp < M; ++grp) {
+                double bout = 0.0;
                 const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc,
-                                                        Fin + (size_t)3 * grp * nc, c, kdx, tab, nf, nth);
+                                                        Fin + (size_t)3 * grp * nc, c, kdx, tab, nf, nth, bout);
                 s.N[grp] = (double)o.n;
+                av[grp] = (double)o.n;
+                av[3 + grp] = bout;
                 io.F[(size_t)(3 * grp) * nc + i] = o.fx;
                 io.F[(size_t)(3 * grp + 1) * nc + i] = o.fy;
                 io.F[(size_t)(3 * grp + 2) * nc + i] = o.fz;
@@ -184,6 +236,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
             fl |= 2u;
         }
     }
+    if (FUSE && io.acct) block_acct(io.acct, av);
     // wave-aggregated enqueue of the unfinished cells
     const bool want = !done;
     const unsigned long long m = __ballot(want);
@@ -210,7 +263,9 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         store_cell<R, M>(io, i, s, T);
         a_acc = (unsigned long long)s.acc;
         a_att = (unsigned long long)s.att;
+        if (io.hist) hist_add(s_hist, s.acc);
     }
+    if (io.hist) hist_flush(s_hist, io.hist);
     block_stats(st, a_acc, a_att, a_att, fl);
 }
 
@@ -229,6 +284,8 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
     bool active = false, exhausted = false;
     unsigned fl = 0;
     unsigned long long a_acc = 0, a_att = 0, a_max = 0;
+    __shared__ unsigned s_hist[64];
+    if (io.hist) hist_init(s_hist);
     while (true) {
         if (!exhausted) {
             const bool need = !active;
@@ -254,6 +311,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
             if (chem_attempt<CM>(k, cc, s, fl)) {
                 const double T = chem_finish<CM>(k, cc, s, fl);
                 store_cell<R, M>(io, cell, s, T);
+                if (io.hist) hist_add(s_hist, s.acc);
                 a_acc += (unsigned long long)s.acc;
                 a_att += (unsigned long long)s.att;
                 a_max = a_max > (unsigned long long)s.att ? a_max : (unsigned long long)s.att;
@@ -261,6 +319,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
             }
         }
     }
+    if (io.hist) hist_flush(s_hist, io.hist);
     block_stats(st, a_acc, a_att, a_max, fl);
 }
 
@@ -296,9 +355,12 @@ static void dispatch_M(int part, const KGrid &g, const KChem &kc, const KChem *d
 
 template <typename R>
 static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *xHeII, double *xHeIII, double *T,
-                         const double *nH, int32_t *nacc, int32_t *natt)
+                         const double *nH, int32_t *nacc, int32_t *natt, double *acct = nullptr,
+                         unsigned long long *hist = nullptr)
 {
     ChemIO<R> io;
+    io.acct = acct;
+    io.hist = hist;
     io.ncell = ncell;
     io.N = (R *)N;
     io.F = (R *)F;
@@ -314,13 +376,13 @@ static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *x
 
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
-                       const QueueView &q, int K, DevStats *stats, hipStream_t s)
+                       const QueueView &q, int K, unsigned long long *hist, DevStats *stats, hipStream_t s)
 {
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt);
+        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist);
         dispatch_M<float, 0, 0>(part, g, kc, dk, dt, 0.f, 0.f, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt);
+        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist);
         dispatch_M<double, 0, 0>(part, g, kc, dk, dt, 0.0, 0.0, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     }
     return hipGetLastError();
@@ -329,17 +391,18 @@ hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, con
 hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, const KChem &kc, const KChem *dk, double dt, const void *Nin,
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
-                             int nth, const QueueView &q, int K, DevStats *stats, hipStream_t s)
+                             int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
+                             DevStats *stats, hipStream_t s)
 {
     const double kdx = dt / g.dx;
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt);
+        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist);
         if (flux)
             dispatch_M<float, 1, 1>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
             dispatch_M<float, 1, 0>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt);
+        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist);
         if (flux)
             dispatch_M<double, 1, 1>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
@@ -438,6 +501,46 @@ __global__ void k_reduce_final(const RedOut *__restrict__ part, int np, RedOut *
         r.minN = part[b].minN < r.minN ? part[b].minN : r.minN;
     }
     *out = r;
+}
+
+// Photon ledger of one step (fixed-order sums; see launch_ledger).
+__global__ __launch_bounds__(256) void k_ledger(int mode, const double *__restrict__ acct, unsigned nblk, int M,
+                                                double V, double dtdx2, const RedOut *__restrict__ red,
+                                                DevStats *__restrict__ st)
+{
+    __shared__ double sh[6][256];
+    const int t = threadIdx.x;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (mode == 2)
+        for (unsigned b = t; b < nblk; b += 256)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) v[q] += acct[(size_t)6 * b + q];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sh[q][t] = v[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sh[q][t] += sh[q][t + o];
+        __syncthreads();
+    }
+    if (t != 0) return;
+    for (int g = 0; g < M; ++g) {
+        if (mode == 0) {
+            st->Tpre[g] = red->photons[g];
+            continue;
+        }
+        const double T0 = mode == 2 ? sh[g][0] * V : st->Tpre[g];
+        st->absorbed[g] += T0 - red->photons[g];
+        if (mode == 2) st->outflow[g] += sh[3 + g][0] * dtdx2;
+    }
+}
+
+hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, int M, double V, double dtdx2,
+                         const RedOut *red, DevStats *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ledger, dim3(1), dim3(256), 0, s, mode, acct, nblk, M, V, dtdx2, red, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,

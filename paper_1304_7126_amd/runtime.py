@@ -209,9 +209,16 @@ class RTContext:
     def stats(self):
         s = capi.RtStats()
         check(lib().rt_get_stats(self._h, ctypes.byref(s)), self._h)
-        return {"photons": list(s.photons)[: self.M], "ionised_H": s.ionised_H, "max_f": s.max_f,
+        M = self.M
+        return {"photons": list(s.photons)[:M], "ionised_H": s.ionised_H, "max_f": s.max_f,
                 "min_N": s.min_N, "substeps_total": s.substeps_total, "attempts_total": s.attempts_total,
-                "attempts_max": s.attempts_max, "flags": s.flags}
+                "attempts_max": s.attempts_max, "flags": s.flags, "injected": list(s.injected)[:M],
+                "absorbed": list(s.absorbed)[:M], "outflow": list(s.outflow)[:M],
+                "substep_hist": list(s.substep_hist)}
+
+    def set_accounting(self, enabled=True):
+        """Photon accounting (injected, absorbed, outflow, substep histogram)."""
+        check(lib().rt_set_accounting(self._h, int(bool(enabled))), self._h)
 
     def set_timing(self, enabled=True):
         check(lib().rt_set_timing(self._h, int(bool(enabled))), self._h)
