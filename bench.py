@@ -21,6 +21,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# VALU wave-instructions per second of the chip: 1,024 SIMDs x 2.4 GHz / 4
+# cycles per wave64 instruction
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
+
+# Counter measurements of k_head<float, 3, 1, 1> on this workload (steps
+# 101-105), valid for the kernel sources they were taken with
+# (profiles/k_head_fused_256cube_3grp_pmc_bytes.md and _pmc_valu.md).
+KERNEL_SOURCES = ("rt_kernels.hip", "rt_cell.h", "rt_device.h", "rt_internal.h")
+COUNTERS_SOURCE_HASH = "361f64844e3b16d8"
+COUNTERS = {"read_bytes": 2641032 * 2 * 1024, "write_bytes": 3159520 * 1024, "valu_wave_instr": 3.314e9,
+            "lane_util": 0.676, "fp64_flops_all_lanes": 1.17e11, "ms": 5.864}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1304_7126_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -259,9 +279,21 @@ def main():
     # algorithmic traffic; the tail re-touches only the queued cells
     t_head = per["head"]
     achieved = step_bytes / (t_head * 1e-3) / 1e9
+    counters_valid = kernel_source_hash() == COUNTERS_SOURCE_HASH and fp32 and n == 256 and args.flux == "hll"
+    traffic = COUNTERS["read_bytes"] + COUNTERS["write_bytes"] if counters_valid else None
+    # the kernel is bound by its VALU issue rate: counter figures (static,
+    # from the profile) and the live duration
+    alu = None
+    if counters_valid:
+        alu = {"valu_issue_frac": COUNTERS["valu_wave_instr"] / (t_head * 1e-3) / VALU_ISSUE_PEAK,
+               "lane_util": COUNTERS["lane_util"],
+               "fp64_active_lane_TFLOPs": COUNTERS["fp64_flops_all_lanes"] * COUNTERS["lane_util"] / (t_head * 1e-3) / 1e12,
+               "fp64_peak_TFLOPs": FP64_VECTOR_PEAK_TFLOPS,
+               "source": "profiles/k_head_fused_256cube_3grp_pmc_valu.md (instruction counts at steps 101-105)"}
     roof = {"kernel": "k_head (transport fused with the first chemistry pass)", "bound": "hbm",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "bytes_per_launch": step_bytes,
+            "traffic": traffic, "traffic_source": "profiles/k_head_fused_256cube_3grp_pmc_bytes.md" if traffic else None,
+            "alu": alu, "bytes_per_launch": step_bytes,
             "ms_per_launch": {"inject": per["inject"], "head": per["head"], "tail": per["tail"]},
             "step_algorithmic_GBps": step_bytes / (ms * 1e-3) / 1e9,
             "step_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
