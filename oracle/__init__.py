@@ -40,9 +40,15 @@ def lib():
         L.or_thermochem.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp,
                                     dp, dp, ip, ip]
         L.or_thermochem.restype = ctypes.c_uint
+        L.or_thermochem_rates.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp, dp,
+                                          dp, dp, dp, ip, ip]
+        L.or_thermochem_rates.restype = ctypes.c_uint
         L.or_thermo_cell.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_double,
                                      dp, dp, dp, dp, ip, ip]
         L.or_thermo_cell.restype = ctypes.c_uint
+        L.or_thermo_cell_rates.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, ctypes.c_double,
+                                           dp, dp, dp, dp, dp, ctypes.POINTER(ctypes.c_double), ip, ip]
+        L.or_thermo_cell_rates.restype = ctypes.c_uint
         L.or_rate.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp]
         L.or_rate.restype = ctypes.c_int
         L.or_eddington.argtypes = [ctypes.c_double, dp, ctypes.c_double, dp]
@@ -54,6 +60,9 @@ def lib():
         L.or_step_cells.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp, dp, dp,
                                     ctypes.c_int, lp, dp, dp, dp, dp, ip, ip]
         L.or_step_cells.restype = ctypes.c_uint
+        L.or_step_cells_smooth.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp, dp, dp,
+                                           dp, ctypes.c_int, lp, dp, dp, dp, dp, ip, ip]
+        L.or_step_cells_smooth.restype = ctypes.c_uint
         _lib = L
     return _lib
 
@@ -204,39 +213,76 @@ class OracleRT:
             return flags, nacc, natt
         return flags
 
-    def step(self, st, dt, ijk=None, ndot=None, want_counts=False):
-        """Operator-split RT step of Sec. 3: injection, transport, thermochemistry."""
+    def thermochem_rates(self, st, dt, Nr, Fr, want_counts=False):
+        """Thermochemistry with the smoothed-RT photon rates Nr (M,...), Fr (M,3,...)."""
+        nacc = np.zeros(st["T"].shape, np.int32)
+        natt = np.zeros(st["T"].shape, np.int32)
+        Nr = np.ascontiguousarray(Nr, np.float64)
+        Fr = np.ascontiguousarray(Fr, np.float64)
+        flags = lib().or_thermochem_rates(ctypes.byref(self.p), float(dt), _dp(st["N"]), _dp(st["F"]), _dp(Nr),
+                                          _dp(Fr), _dp(st["xHII"]), _dp(st["xHeII"]), _dp(st["xHeIII"]),
+                                          _dp(st["T"]), _dp(st["nH"]), _ip(nacc), _ip(natt))
+        if want_counts:
+            return flags, nacc, natt
+        return flags
+
+    def step(self, st, dt, ijk=None, ndot=None, want_counts=False, smooth=False):
+        """Operator-split RT step of Sec. 3: injection, transport, thermochemistry.
+        With smooth (Sec. 4.4) the chemistry starts from the state before
+        injection and transport and takes their effect as constant rates
+        (eqs. smoothrate1, smoothrate2)."""
+        if smooth:
+            N0 = st["N"].copy()
+            F0 = st["F"].copy()
         if ijk is not None and len(ijk):
             self.inject(st, dt, ijk, ndot)
         self.transport(st, dt)
-        return self.thermochem(st, dt, want_counts=want_counts)
+        if not smooth:
+            return self.thermochem(st, dt, want_counts=want_counts)
+        Nr = (st["N"] - N0) / dt
+        Fr = (st["F"] - F0) / dt
+        st["N"], st["F"] = N0, F0
+        return self.thermochem_rates(st, dt, Nr, Fr, want_counts=want_counts)
 
-    def step_cells(self, st, dt, cells):
+    def step_cells(self, st, dt, cells, N_pre=None):
         """Transport + thermochemistry of the listed cells (linear indices)
-        from an already-injected source state; returns per-cell results."""
+        from an already-injected source state; returns per-cell results.
+        With N_pre (the photon densities before the injection) the step is
+        smoothed (Sec. 4.4)."""
         cells = np.ascontiguousarray(cells, dtype=np.int64)
         n = cells.size
         M = self.M
         out = {"N": np.zeros((n, M)), "F": np.zeros((n, M, 3)), "x": np.zeros((n, 3)), "T": np.zeros(n),
                "nacc": np.zeros(n, np.int32), "natt": np.zeros(n, np.int32)}
         c64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
-        arrs = [c64(st[k]) for k in ("N", "F", "xHII", "xHeII", "xHeIII", "T", "nH")]
-        fl = lib().or_step_cells(ctypes.byref(self.p), float(dt), *[_dp(a) for a in arrs], int(n),
-                                 cells.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _dp(out["N"]),
-                                 _dp(out["F"]), _dp(out["x"]), _dp(out["T"]), _ip(out["nacc"]), _ip(out["natt"]))
+        arrs = [c64(st[k]) for k in ("N", "F")]
+        arrs.append(c64(N_pre) if N_pre is not None else None)
+        arrs += [c64(st[k]) for k in ("xHII", "xHeII", "xHeIII", "T", "nH")]
+        fl = lib().or_step_cells_smooth(ctypes.byref(self.p), float(dt),
+                                        *[_dp(a) if a is not None else None for a in arrs], int(n),
+                                        cells.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), _dp(out["N"]),
+                                        _dp(out["F"]), _dp(out["x"]), _dp(out["T"]), _ip(out["nacc"]),
+                                        _ip(out["natt"]))
         out["flags"] = fl
         return out
 
-    def thermo_cell(self, dt, nH, N, F, x, T):
-        """One cell (arrays of length M / 3M / 3): returns new values and counts."""
+    def thermo_cell(self, dt, nH, N, F, x, T, Nr=None, Fr=None):
+        """One cell (arrays of length M / 3M / 3): returns new values and counts.
+        Nr (M), Fr (3M): the smoothed-RT photon rates (Sec. 4.4), or None."""
         N = np.array(N, dtype=np.float64)
         F = np.array(F, dtype=np.float64)
         xs = np.array(x, dtype=np.float64)
         Tc = ctypes.c_double(float(T))
         a = ctypes.c_int()
         t = ctypes.c_int()
-        fl = lib().or_thermo_cell(ctypes.byref(self.p), float(dt), float(nH), _dp(N), _dp(F), _dp(xs),
-                                  ctypes.byref(Tc), ctypes.byref(a), ctypes.byref(t))
+        if Nr is None and Fr is None:
+            fl = lib().or_thermo_cell(ctypes.byref(self.p), float(dt), float(nH), _dp(N), _dp(F), _dp(xs),
+                                      ctypes.byref(Tc), ctypes.byref(a), ctypes.byref(t))
+        else:
+            nr = np.array(Nr if Nr is not None else np.zeros(N.shape), dtype=np.float64)
+            fr = np.array(Fr if Fr is not None else np.zeros(F.shape), dtype=np.float64)
+            fl = lib().or_thermo_cell_rates(ctypes.byref(self.p), float(dt), float(nH), _dp(N), _dp(F), _dp(nr),
+                                            _dp(fr), _dp(xs), ctypes.byref(Tc), ctypes.byref(a), ctypes.byref(t))
         return dict(N=N, F=F, x=xs, T=Tc.value, nacc=a.value, natt=t.value, flags=fl)
 
     def face_flux(self, d, UL, UR):

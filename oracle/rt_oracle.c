@@ -513,8 +513,20 @@ static double relchg(double a, double b, double floor)
 
 /* One cell over dt_RT.  N[g], F[g][3] in/out; xs = {x_HII, x_HeII, x_HeIII}
  * in/out; T in/out; nacc/natt: accepted substeps / attempts.  Returns flags. */
+unsigned or_thermo_cell_rates(const or_params *p, double dtRT, double nH, double *N, double *F,
+                              const double *Nr, const double *Fr, double *xs, double *T, int *nacc, int *natt);
+
 unsigned or_thermo_cell(const or_params *p, double dtRT, double nH, double *N, double *F,
                         double *xs, double *T, int *nacc, int *natt)
+{
+    return or_thermo_cell_rates(p, dtRT, nH, N, F, NULL, NULL, xs, T, nacc, natt);
+}
+
+/* As or_thermo_cell, with the photon-density and flux rates of smoothed RT
+ * (Sec. 4.4, eqs. thchem_N_smooth, thchem_F_smooth): Nr[g], Fr[3g+d] are
+ * added to the photon equations of App. A task 1 (NULL: none). */
+unsigned or_thermo_cell_rates(const or_params *p, double dtRT, double nH, double *N, double *F,
+                              const double *Nr, const double *Fr, double *xs, double *T, int *nacc, int *natt)
 {
     const int M = p->M;
     const double cr = p->c_r;
@@ -531,8 +543,9 @@ unsigned or_thermo_cell(const or_params *p, double dtRT, double nH, double *N, d
     /* a cell with a non-finite input is reported and left as it is */
     int finite_in = isfinite(*T) && isfinite(x) && isfinite(y2) && isfinite(y3);
     for (int g = 0; g < M; g++) {
-        finite_in = finite_in && isfinite(N[g]);
-        for (int d = 0; d < 3; d++) finite_in = finite_in && isfinite(F[3 * g + d]);
+        finite_in = finite_in && isfinite(N[g]) && (!Nr || isfinite(Nr[g]));
+        for (int d = 0; d < 3; d++)
+            finite_in = finite_in && isfinite(F[3 * g + d]) && (!Fr || isfinite(Fr[3 * g + d]));
     }
     if (!finite_in) {
         *nacc = 0;
@@ -559,8 +572,15 @@ unsigned or_thermo_cell(const or_params *p, double dtRT, double nH, double *N, d
         double Nn[3], Fn[3][3];
         for (int g = 0; g < M; g++) {
             double D = cr * (p->sigN[g][0] * nHI + p->sigN[g][1] * nHeI + p->sigN[g][2] * nHeII);
-            Nn[g] = N[g] / (1.0 + h * D);
-            for (int d = 0; d < 3; d++) Fn[g][d] = F[3 * g + d] / (1.0 + h * D);
+            /* eq. SIE photons, with the smoothed-RT rates when given */
+            Nn[g] = (Nr ? N[g] + h * Nr[g] : N[g]) / (1.0 + h * D);
+            /* a negative rate can take the smoothed update below zero (its
+             * steady state Nr/D is then negative): no photon density is
+             * negative, so it stops at zero.  Above N_floor the 10% check
+             * below refuses such a substep anyway. */
+            if (Nr && Nn[g] < 0.0) Nn[g] = 0.0;
+            for (int d = 0; d < 3; d++)
+                Fn[g][d] = (Fr ? F[3 * g + d] + h * Fr[3 * g + d] : F[3 * g + d]) / (1.0 + h * D);
             r = relchg(Nn[g], N[g], p->N_floor);
             if (r > 0.1) fail = 1;
             if (r > maxrel) maxrel = r;
@@ -695,26 +715,31 @@ unsigned or_thermo_cell(const or_params *p, double dtRT, double nH, double *N, d
 }
 
 /* Thermochemistry over the whole grid.  nacc/natt may be NULL. */
-unsigned or_thermochem(const or_params *p, double dt, double *N, double *F, double *xHII,
-                       double *xHeII, double *xHeIII, double *T, const double *nH,
-                       int *nacc, int *natt)
+/* Thermochemistry over the whole grid, with the smoothed-RT rates
+ * Nr[g*nc + i], Fr[(3g+d)*nc + i] when they are not NULL.  nacc/natt may be NULL. */
+unsigned or_thermochem_rates(const or_params *p, double dt, double *N, double *F, const double *Nr,
+                             const double *Fr, double *xHII, double *xHeII, double *xHeIII, double *T,
+                             const double *nH, int *nacc, int *natt)
 {
     size_t nc = (size_t)p->nx * p->ny * p->nz;
     unsigned flags = 0;
     const int M = p->M;
 #pragma omp parallel for schedule(dynamic, 256) reduction(| : flags)
     for (long long i = 0; i < (long long)nc; i++) {
-        double Nc[3], Fc[9], xs[3], Tc;
+        double Nc[3], Fc[9], Nrc[3], Frc[9], xs[3], Tc;
         for (int g = 0; g < M; g++) {
             Nc[g] = N[(size_t)g * nc + i];
             for (int d = 0; d < 3; d++) Fc[3 * g + d] = F[(size_t)(3 * g + d) * nc + i];
+            if (Nr) Nrc[g] = Nr[(size_t)g * nc + i];
+            if (Fr)
+                for (int d = 0; d < 3; d++) Frc[3 * g + d] = Fr[(size_t)(3 * g + d) * nc + i];
         }
         xs[0] = xHII[i];
         xs[1] = xHeII[i];
         xs[2] = xHeIII[i];
         Tc = T[i];
         int a, t;
-        flags |= or_thermo_cell(p, dt, nH[i], Nc, Fc, xs, &Tc, &a, &t);
+        flags |= or_thermo_cell_rates(p, dt, nH[i], Nc, Fc, Nr ? Nrc : NULL, Fr ? Frc : NULL, xs, &Tc, &a, &t);
         for (int g = 0; g < M; g++) {
             N[(size_t)g * nc + i] = Nc[g];
             for (int d = 0; d < 3; d++) F[(size_t)(3 * g + d) * nc + i] = Fc[3 * g + d];
@@ -729,15 +754,39 @@ unsigned or_thermochem(const or_params *p, double dt, double *N, double *F, doub
     return flags;
 }
 
+unsigned or_thermochem(const or_params *p, double dt, double *N, double *F, double *xHII,
+                       double *xHeII, double *xHeIII, double *T, const double *nH,
+                       int *nacc, int *natt)
+{
+    return or_thermochem_rates(p, dt, N, F, NULL, NULL, xHII, xHeII, xHeIII, T, nH, nacc, natt);
+}
+
 /* Transport and thermochemistry of selected cells only (for sampled checks
  * of large grids): for each listed cell, the transport of every group from
  * the source arrays (N, F: already injected), then its thermochemistry.
  * Outputs per listed cell: Nout[c*M+g], Fout[(c*M+g)*3+d], xs[c*3+0..2],
  * Tout[c], nacc[c], natt[c].  Returns the OR of the chemistry flags. */
+unsigned or_step_cells_smooth(const or_params *p, double dt, const double *N, const double *F,
+                              const double *Npre, const double *xHII, const double *xHeII, const double *xHeIII,
+                              const double *T, const double *nH, int ncells, const long long *cells, double *Nout,
+                              double *Fout, double *xs, double *Tout, int *nacc, int *natt);
+
 unsigned or_step_cells(const or_params *p, double dt, const double *N, const double *F, const double *xHII,
                        const double *xHeII, const double *xHeIII, const double *T, const double *nH, int ncells,
                        const long long *cells, double *Nout, double *Fout, double *xs, double *Tout, int *nacc,
                        int *natt)
+{
+    return or_step_cells_smooth(p, dt, N, F, NULL, xHII, xHeII, xHeIII, T, nH, ncells, cells, Nout, Fout, xs, Tout,
+                                nacc, natt);
+}
+
+/* As or_step_cells; with Npre (layout of N: the photon densities before the
+ * injection) the step is smoothed (Sec. 4.4): the chemistry starts from
+ * Npre and the source flux F and takes the transport result as rates. */
+unsigned or_step_cells_smooth(const or_params *p, double dt, const double *N, const double *F,
+                              const double *Npre, const double *xHII, const double *xHeII, const double *xHeIII,
+                              const double *T, const double *nH, int ncells, const long long *cells, double *Nout,
+                              double *Fout, double *xs, double *Tout, int *nacc, int *natt)
 {
     int nx = p->nx, ny = p->ny;
     size_t nc = (size_t)p->nx * p->ny * p->nz;
@@ -768,7 +817,23 @@ unsigned or_step_cells(const or_params *p, double dt, const double *N, const dou
         x3[2] = xHeIII[i];
         Tc = T[i];
         int a, t;
-        flags |= or_thermo_cell(p, dt, nH[i], Nc, Fc, x3, &Tc, &a, &t);
+        if (Npre) {
+            /* eqs. smoothrate1, smoothrate2 */
+            double Nr[3], Fr[9];
+            for (int g = 0; g < p->M; g++) {
+                double N0 = Npre[(size_t)g * nc + (size_t)i];
+                Nr[g] = (Nc[g] - N0) / dt;
+                Nc[g] = N0;
+                for (int d = 0; d < 3; d++) {
+                    double F0 = F[(size_t)(3 * g + d) * nc + (size_t)i];
+                    Fr[3 * g + d] = (Fc[3 * g + d] - F0) / dt;
+                    Fc[3 * g + d] = F0;
+                }
+            }
+            flags |= or_thermo_cell_rates(p, dt, nH[i], Nc, Fc, Nr, Fr, x3, &Tc, &a, &t);
+        } else {
+            flags |= or_thermo_cell(p, dt, nH[i], Nc, Fc, x3, &Tc, &a, &t);
+        }
         for (int g = 0; g < p->M; g++) {
             Nout[(size_t)c * p->M + g] = Nc[g];
             for (int d = 0; d < 3; d++) Fout[((size_t)c * p->M + g) * 3 + d] = Fc[3 * g + d];
