@@ -96,7 +96,12 @@ typedef struct {
  *   x_min       floor on x_HII (1e-6 in the paper's tests)
  *   N_floor     photon densities <= N_floor skip the 10% check (0: only
  *               empty groups skip it, as written in App. A)
- *   max_attempts cap on chemistry attempts per cell per step (>= 1) */
+ *   max_attempts cap on chemistry attempts per cell per step (>= 1)
+ *   smooth      smoothed RT (Sec. 4.4): 1 = the thermochemistry starts from
+ *               N, F before the step's injection and transport and adds
+ *               their change as constant rates (eqs. thchem_N_smooth,
+ *               thchem_F_smooth, smoothrate1, smoothrate2); 0 = plain
+ *               operator splitting.  The batch and the adjoint need 0. */
 typedef struct {
     int flux;
     int otsa;
@@ -108,6 +113,7 @@ typedef struct {
     double x_min;
     double N_floor;
     long long max_attempts;
+    int smooth;
 } rt_params;
 
 /* Caller-owned state.
@@ -188,14 +194,22 @@ rt_status rt_set_sources(rt_ctx *ctx, int n, const int32_t *ijk, const double *n
  * dt_courant, with the factor 0.8 of the paper's tests). */
 rt_status rt_courant_dt(const rt_ctx *ctx, double courant, double *dt);
 
-/* Injection: N_g(cell) += ndot_g dt / dx^3 in the current set. */
+/* Injection: N_g(cell) += ndot_g dt / dx^3 in the current set.
+ * With smooth = 1 a step's calls must come in the order rt_inject (at most
+ * once, optional), rt_transport, rt_thermochem; the library keeps each
+ * source cell's N from before the injection, and a call out of that order
+ * returns RT_ESTATE.  rt_bind, rt_set_current and rt_set_sources start a new
+ * step. */
 rt_status rt_inject(rt_ctx *ctx, double dt);
 
 /* Transport (Sec. 3.2) of every group over dt from the current set into the
  * other set, which then becomes current.  dt must satisfy dt <= dx/(3 c_r). */
 rt_status rt_transport(rt_ctx *ctx, double dt);
 
-/* Thermochemistry (App. A) of every cell over dt on the current set. */
+/* Thermochemistry (App. A) of every cell over dt on the current set.  With
+ * smooth = 1 each cell starts from N^t, F^t (the other set, and for source
+ * cells N before the injection) and receives (N' - N^t)/dt and
+ * (F' - F^t)/dt, N', F' being the current set, as constant rates (Sec. 4.4). */
 rt_status rt_thermochem(rt_ctx *ctx, double dt);
 
 /* nsteps full steps: injection, transport, thermochemistry (Sec. 3).

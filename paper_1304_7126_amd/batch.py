@@ -48,7 +48,8 @@ class RTBatch:
     method parameters common to all boxes."""
 
     def __init__(self, grids, groups, flux=0, isothermal=False, X=0.76, Y=0.24, gamma=5.0 / 3.0, a_exp=1.0,
-                 x_min=1e-6, N_floor=0.0, max_attempts=100000, fp32=False, device="cuda", counters=False):
+                 x_min=1e-6, N_floor=0.0, max_attempts=100000, fp32=False, device="cuda", counters=False,
+                 smooth=False):
         L = lib()
         nb = len(grids)
         cg = (capi.RtGrid * nb)()
@@ -69,6 +70,7 @@ class RTBatch:
         p.prec = capi.RT_PREC_FP32_TRANSPORT if fp32 else capi.RT_PREC_FP64
         p.X, p.Y, p.gamma, p.a_exp = float(X), float(Y), float(gamma), float(a_exp)
         p.x_min, p.N_floor, p.max_attempts = float(x_min), float(N_floor), int(max_attempts)
+        p.smooth = int(bool(smooth))
         h = ctypes.c_void_p()
         _check(L.rt_batch_init(nb, cg, cr, ctypes.byref(p), ctypes.byref(h)), None)
         self._h = h

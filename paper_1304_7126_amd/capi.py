@@ -44,7 +44,7 @@ class RtParams(ctypes.Structure):
     _fields_ = [("flux", ctypes.c_int), ("otsa", ctypes.c_int), ("isothermal", ctypes.c_int),
                 ("prec", ctypes.c_int), ("X", ctypes.c_double), ("Y", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("a_exp", ctypes.c_double), ("x_min", ctypes.c_double),
-                ("N_floor", ctypes.c_double), ("max_attempts", ctypes.c_longlong)]
+                ("N_floor", ctypes.c_double), ("max_attempts", ctypes.c_longlong), ("smooth", ctypes.c_int)]
 
 
 class RtState(ctypes.Structure):

@@ -34,6 +34,13 @@ struct rt_ctx {
     int nsrc_in = 0;                 // sources as given (for the injection adjoint)
     int32_t *src_in_cell = nullptr;
     double *src_in_rate = nullptr;   // group-0 rate of each given source
+    // smoothed RT: source index per cell, each source cell's N before the
+    // injection, and where the step stands (0: nothing yet, 1: injected,
+    // 2: transported; injected says whether 1 preceded 2)
+    int32_t *src_map = nullptr;
+    double *src_prev = nullptr;
+    int sm_phase = 0;
+    bool sm_injected = false;
     DevStats *dstats = nullptr;
     RedOut *dred = nullptr;
     unsigned qcap = 0;               // chemistry queue capacity (cells)
@@ -338,6 +345,7 @@ static rt_status validate(const rt_grid *g, const rt_groups *gr, const rt_params
     if (!(p->x_min > 0) || !(p->x_min < 1)) { err = "x_min must be in (0,1)"; return RT_EINVAL; }
     if (!(p->N_floor >= 0)) { err = "N_floor must be >= 0"; return RT_EINVAL; }
     if (p->max_attempts < 1) { err = "max_attempts must be >= 1"; return RT_EINVAL; }
+    if (p->smooth != 0 && p->smooth != 1) { err = "smooth must be 0 or 1"; return RT_EINVAL; }
     return RT_OK;
 }
 
@@ -399,6 +407,11 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     if (e == hipSuccess) e = hipMalloc((void **)&c->dred, sizeof(RedOut));
     if (e == hipSuccess) e = hipMalloc((void **)&c->dkchem, sizeof(KChem));
     if (e == hipSuccess) e = hipMemcpy(c->dkchem, &c->kchem, sizeof(KChem), hipMemcpyHostToDevice);
+    if (e == hipSuccess && params->smooth) {
+        e = hipMalloc((void **)&c->src_map, c->grid.ncell * sizeof(int32_t));
+        if (e == hipSuccess) e = launch_source_map(c->src_map, c->grid.ncell, nullptr, 0, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
     if (e != hipSuccess) {
         g_init_err = std::string("device table allocation failed: ") + hipGetErrorString(e);
         rt_free(c);
@@ -418,14 +431,15 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
 
 static size_t scratch_need(const rt_ctx *c)
 {
-    return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max) + acct_bytes(c->grid.ncell);
+    return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max, c->params.smooth != 0) +
+           acct_bytes(c->grid.ncell);
 }
 
 // accounting partials: after the reduction partials and the queue
 static double *acct_part(const rt_ctx *c)
 {
     return (double *)((char *)c->st.scratch + ((reduction_scratch_bytes() + 255) & ~(size_t)255) +
-                      queue_bytes(c->qcap_max));
+                      queue_bytes(c->qcap_max, c->params.smooth != 0));
 }
 
 extern "C" size_t rt_scratch_bytes(const rt_ctx *c)
@@ -446,6 +460,7 @@ extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
     c->st = *s;
     c->bound = true;
     c->cur = 0;
+    c->sm_phase = 0;
     return RT_OK;
 }
 
@@ -463,6 +478,7 @@ extern "C" rt_status rt_set_current(rt_ctx *c, int set)
     if (!c) return RT_EINVAL;
     if (set != 0 && set != 1) RT_FAIL(c, RT_EINVAL, "set must be 0 or 1");
     c->cur = set;
+    c->sm_phase = 0;
     return RT_OK;
 }
 
@@ -493,13 +509,18 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
             for (int g = 0; g < M; ++g) rates[pos * M + g] += ndot[(size_t)s * M + g];
         }
     }
+    // work in flight may still read the old tables
+    RT_HIP(c, hipStreamSynchronize(c->stream));
     if (c->src_cell) { (void)hipFree(c->src_cell); c->src_cell = nullptr; }
     if (c->src_rate) { (void)hipFree(c->src_rate); c->src_rate = nullptr; }
     if (c->src_in_cell) { (void)hipFree(c->src_in_cell); c->src_in_cell = nullptr; }
     if (c->src_in_rate) { (void)hipFree(c->src_in_rate); c->src_in_rate = nullptr; }
+    if (c->src_prev) { (void)hipFree(c->src_prev); c->src_prev = nullptr; }
     c->nsrc = 0;
     c->nsrc_in = 0;
     c->src_rate_host.clear();
+    c->sm_phase = 0;
+    if (c->src_map) RT_HIP(c, launch_source_map(c->src_map, c->grid.ncell, nullptr, 0, c->stream));
     if (cells.empty()) return RT_OK;
     {
         std::vector<int32_t> in_cell(n);
@@ -521,6 +542,10 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     RT_HIP(c, hipMemcpy(c->src_rate, rates.data(), rates.size() * sizeof(double), hipMemcpyHostToDevice));
     c->nsrc = (int)cells.size();
     c->src_rate_host = rates;
+    if (c->src_map) {
+        RT_HIP(c, hipMalloc((void **)&c->src_prev, rates.size() * sizeof(double)));
+        RT_HIP(c, launch_source_map(c->src_map, c->grid.ncell, c->src_cell, c->nsrc, c->stream));
+    }
     return RT_OK;
 }
 
@@ -552,13 +577,18 @@ static rt_status check_ready(rt_ctx *c, double dt)
 static rt_status do_inject(rt_ctx *c, double dt)
 {
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+    if (c->params.smooth) {
+        if (c->sm_phase != 0) RT_FAIL(c, RT_ESTATE, "smoothed RT: one injection per step, before the transport");
+        if (c->nsrc == 0) return RT_OK;
+        c->sm_phase = 1;
+    }
     if (c->nsrc == 0) return RT_OK;
     if (c->acct)
         for (int q = 0; q < c->nsrc; ++q)
             for (int g = 0; g < c->groups.M; ++g) c->injected[g] += c->src_rate_host[(size_t)q * c->groups.M + g] * dt;
     return timed(c, TM_INJECT, [&]() -> rt_status {
         RT_HIP(c, launch_inject(c->fp32, c->st.N[c->cur], c->grid.ncell, c->groups.M, c->nsrc, c->src_cell,
-                                c->src_rate, dt / V, c->stream));
+                                c->src_rate, dt / V, c->params.smooth ? c->src_prev : nullptr, c->stream));
         return RT_OK;
     });
 }
@@ -567,6 +597,8 @@ static rt_status do_transport(rt_ctx *c, double dt)
 {
     const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
     if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    if (c->params.smooth && c->sm_phase == 2)
+        RT_FAIL(c, RT_ESTATE, "smoothed RT: the step's transport has run; its thermochemistry comes next");
     const int s = c->cur, d = 1 - c->cur;
     rt_status r = timed(c, TM_TRANSPORT, [&]() -> rt_status {
         RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, c->groups.c_r, dt, c->st.N[s],
@@ -577,6 +609,10 @@ static rt_status do_transport(rt_ctx *c, double dt)
     if (r != RT_OK) return r;
     c->cur = d;
     c->acct_pending = c->acct;
+    if (c->params.smooth) {
+        c->sm_injected = c->sm_phase == 1;
+        c->sm_phase = 2;
+    }
     return RT_OK;
 }
 
@@ -601,8 +637,26 @@ static rt_status acct_close(rt_ctx *c, double dt)
     return RT_OK;
 }
 
+// smoothed RT: the radiation set before the step and the source table
+static SmoothArgs smooth_args(const rt_ctx *c, int pre_set, bool injected)
+{
+    SmoothArgs a;
+    a.N = c->st.N[pre_set];
+    a.F = c->st.F[pre_set];
+    a.map = injected ? c->src_map : nullptr;
+    a.prev = c->src_prev;
+    return a;
+}
+
 static rt_status do_chem(rt_ctx *c, double dt)
 {
+    SmoothArgs sa;
+    if (c->params.smooth) {
+        if (c->sm_phase != 2) RT_FAIL(c, RT_ESTATE, "smoothed RT: the thermochemistry needs the step's transport first");
+        sa = smooth_args(c, 1 - c->cur, c->sm_injected);
+        c->sm_phase = 0;
+    }
+    const SmoothArgs *sm = c->params.smooth ? &sa : nullptr;
     const QueueView q = queue_view(c->st.scratch, c->qcap, c->qcap_max);
     if (c->acct && !c->acct_pending) {
         // no transport before this chemistry: its input totals come from a reduction
@@ -615,7 +669,7 @@ static rt_status do_chem(rt_ctx *c, double dt)
         rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
             RT_HIP(c, launch_chem(part, c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
                                   c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, q,
-                                  c->head_attempts, hist, c->dstats, c->stream));
+                                  c->head_attempts, hist, sm, c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
@@ -630,6 +684,13 @@ static rt_status do_fused(rt_ctx *c, double dt)
     const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
     if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
     const int s = c->cur, d = 1 - c->cur;
+    SmoothArgs sa;
+    if (c->params.smooth) {
+        if (c->sm_phase > 1) RT_FAIL(c, RT_ESTATE, "smoothed RT: the step's transport has already run");
+        sa = smooth_args(c, s, c->sm_phase == 1);
+        c->sm_phase = 0;
+    }
+    const SmoothArgs *sm = c->params.smooth ? &sa : nullptr;
     const QueueView q = queue_view(c->st.scratch, c->qcap, c->qcap_max);
     for (int part = 1; part <= 2; ++part) {
         rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
@@ -637,7 +698,7 @@ static rt_status do_fused(rt_ctx *c, double dt)
                                         c->st.N[d], c->st.F[d], c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T,
                                         c->st.nH, c->st.nacc, c->st.natt, c->hll_dev, c->nf, c->nth, q,
                                         c->head_attempts, c->acct ? acct_part(c) : nullptr,
-                                        c->acct ? c->dstats->hist : nullptr, c->dstats, c->stream));
+                                        c->acct ? c->dstats->hist : nullptr, sm, c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
@@ -781,6 +842,7 @@ static rt_status adj_supported(rt_ctx *c, double dt)
     if (c->params.Y != 0.0) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs hydrogen-only gas (Y = 0)");
     if (c->params.flux != RT_FLUX_GLF) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the GLF flux");
     if (c->fp32) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs RT_PREC_FP64");
+    if (c->params.smooth) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs smooth = 0");
     for (int f = 0; f < 6; ++f)
         if (c->grid.bc[f] != RT_BC_PERIODIC) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs periodic boundaries");
     const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
@@ -889,6 +951,8 @@ extern "C" void rt_free(rt_ctx *c)
     if (c->src_rate) (void)hipFree(c->src_rate);
     if (c->src_in_cell) (void)hipFree(c->src_in_cell);
     if (c->src_in_rate) (void)hipFree(c->src_in_rate);
+    if (c->src_map) (void)hipFree(c->src_map);
+    if (c->src_prev) (void)hipFree(c->src_prev);
     if (c->dstats) (void)hipFree(c->dstats);
     if (c->dred) (void)hipFree(c->dred);
     if (c->dkchem) (void)hipFree(c->dkchem);

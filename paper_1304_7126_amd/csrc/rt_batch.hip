@@ -445,6 +445,10 @@ extern "C" rt_status rt_batch_init(int nbox, const rt_grid *grids, const rt_grou
             return RT_EINVAL;
         }
     }
+    if (params->smooth) {
+        g_batch_err = "the batch runs without smoothed RT (smooth = 0)";
+        return RT_EUNSUPPORTED;
+    }
     if (params->otsa != 1) {
         g_batch_err = "only the on-the-spot approximation (otsa = 1) is supported";
         return RT_EUNSUPPORTED;

@@ -3,6 +3,8 @@
 // the transport of one cell (Sec. 3.2) and one attempt of the subcycled
 // thermochemistry (App. A), plus the queue of cells still subcycling.
 #pragma once
+#include <type_traits>
+
 #include "rt_device.h"
 #include "rt_internal.h"
 
@@ -198,6 +200,17 @@ struct CS {
     int acc, att;   // accepted substeps, attempts
 };
 
+// Smoothed RT (Sec. 4.4): the cell starts from its photon density before
+// injection and transport, and their change over dt_RT enters every substep
+// as the constant rate Nr (eqs. thchem_N_smooth, smoothrate1).  The flux
+// obeys the same linear update with the rate (F' - F^t)/dt_RT (eqs.
+// thchem_F_smooth, smoothrate2), so after the accepted substeps h_k with
+// absorption factors r_k = 1/(1 + h_k D_k) it is fs F^t + fb (F' - F^t)/dt_RT
+// with fs = prod r_k and fb <- (fb + h_k) r_k; the state carries fb.
+struct CSR : CS {
+    double Nr[3], fb[3];
+};
+
 // Every chemistry kernel runs the attempt with three groups; groups a grid
 // does not have carry zero photons and zero cross sections, which leaves
 // every sum and check exactly as with fewer groups.  One instantiation for
@@ -224,14 +237,18 @@ __device__ __forceinline__ CC make_cc(const KChem &k, double nH, double T)
 
 // Returns false (and leaves the cell untouched) when an input is not finite;
 // fin says whether the cell's fluxes are finite.
-template <int M>
-__device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, bool fin, CS &s)
+template <int M, bool SM = false, class St>
+__device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, bool fin, St &s)
 {
     bool ok = fin && isfinite(T) && isfinite(s.x) && isfinite(s.y2) && isfinite(s.y3);
 #pragma unroll
     for (int g = 0; g < M; ++g) {
         ok = ok && isfinite(s.N[g]);
         s.fs[g] = 1.0;
+        if constexpr (SM) {
+            ok = ok && isfinite(s.Nr[g]);
+            s.fb[g] = 0.0;
+        }
     }
     s.Tmu = T / mu_of(k, s.x, s.y2, s.y3);
     s.rem = ok ? dt : 0.0;
@@ -246,8 +263,8 @@ __device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, b
 // advances by h, and the next h doubles when every relative change was
 // below 5%.  Returns true when the cell has filled dt_RT (or reached the
 // attempt cap, flag bit 0).
-template <int M>
-__device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s, unsigned &flags)
+template <int M, bool SM = false, class St>
+__device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s, unsigned &flags)
 {
     if (s.att >= k.max_att) {
         flags |= 1u;
@@ -272,7 +289,12 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s
     for (int g = 0; g < M; ++g) {
         const double D = k.csN[g][0] * nHI + k.csN[g][1] * nHeI + k.csN[g][2] * nHeII;
         rd[g] = 1.0 / (1.0 + h * D);
-        Nn[g] = s.N[g] * rd[g];
+        if constexpr (SM) {
+            // a negative rate may take the update below zero: it stops there
+            const double nn = (s.N[g] + h * s.Nr[g]) * rd[g];
+            Nn[g] = nn < 0.0 ? 0.0 : nn;
+        } else
+            Nn[g] = s.N[g] * rd[g];
         if (s.N[g] > k.N_floor) {
             fail |= rel_above(Nn[g], s.N[g], 0.1);
             small &= fabs(Nn[g] - s.N[g]) < 0.05 * s.N[g];
@@ -383,6 +405,7 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s
     for (int g = 0; g < M; ++g) {
         s.N[g] = Nn[g];
         s.fs[g] *= rd[g];
+        if constexpr (SM) s.fb[g] = (s.fb[g] + h) * rd[g];
     }
     s.x = xn;
     s.y2 = y2n;
@@ -394,8 +417,8 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, CS &s
     return !(s.rem > 0.0);
 }
 
-template <int M>
-__device__ __forceinline__ double chem_finish(const KChem &k, const CC &cc, const CS &s, unsigned &flags)
+template <int M, class S>
+__device__ __forceinline__ double chem_finish(const KChem &k, const CC &cc, const S &s, unsigned &flags)
 {
     const double T = k.isothermal ? cc.Tiso : s.Tmu * mu_of(k, s.x, s.y2, s.y3);
 #pragma unroll
@@ -409,10 +432,36 @@ __device__ __forceinline__ double chem_finish(const KChem &k, const CC &cc, cons
 
 // Queue of cells still subcycling after the head pass (structure of arrays
 // in caller scratch): the cell index, the attempt counters, and the partial
-// state {N[3], fs[3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}.
+// state {N[3], fs[3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}, followed with
+// smoothed RT by {Nr[3], fb[3]}.
 constexpr int QV = 12;
+constexpr int QV_SMOOTH = 18;
 
-__device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t cell, const CS &s)
+__device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CS &) {}
+__device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CSR &s)
+{
+    double *v = q.v + p;
+    const size_t c = q.stride;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        v[(size_t)(QV + g) * c] = s.Nr[g];
+        v[(size_t)(QV + 3 + g) * c] = s.fb[g];
+    }
+}
+__device__ __forceinline__ void q_load_rates(const QueueView &q, uint32_t p, CS &) {}
+__device__ __forceinline__ void q_load_rates(const QueueView &q, uint32_t p, CSR &s)
+{
+    const double *v = q.v + p;
+    const size_t c = q.stride;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        s.Nr[g] = v[(size_t)(QV + g) * c];
+        s.fb[g] = v[(size_t)(QV + 3 + g) * c];
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t cell, const S &s)
 {
     q.cell[p] = (int32_t)cell;
     q.acc[p] = s.acc;
@@ -430,9 +479,11 @@ __device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t
     v[9 * c] = s.Tmu;
     v[10 * c] = s.rem;
     v[11 * c] = s.h;
+    q_store_rates(q, p, s);
 }
 
-__device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, CS &s)
+template <class S>
+__device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, S &s)
 {
     s.acc = q.acc[p];
     s.att = q.att[p];
@@ -449,13 +500,30 @@ __device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, CS &s
     s.Tmu = v[9 * c];
     s.rem = v[10 * c];
     s.h = v[11 * c];
+    q_load_rates(q, p, s);
     return (uint32_t)q.cell[p];
 }
 
-// Write a finished cell: N, the flux in the destination scaled by fs, the
-// gas state and the counters.
-template <typename R, int M>
-__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const CS &s, double T)
+// Flux of group g of a finished cell from the transported flux fp in the
+// destination (and, smoothed, the pre-step flux ft of the source set).
+template <typename R>
+__device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CS &s, int g, size_t j, R fp)
+{
+    return (R)((double)fp * s.fs[g]);
+}
+template <typename R>
+__device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CSR &s, int g, size_t j, R fp)
+{
+    // a cell that accepted no substep keeps its pre-step state
+    const double ft = (double)io.sm.F[j];
+    if (s.acc == 0) return (R)ft;
+    return (R)(s.fs[g] * ft + s.fb[g] * (((double)fp - ft) / io.sm.dt));
+}
+
+// Write a finished cell: N, the flux in the destination scaled by fs (with
+// smoothed RT: fs F^t + fb (F' - F^t)/dt_RT), the gas state and the counters.
+template <typename R, int M, class S>
+__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const S &s, double T)
 {
     const size_t nc = io.ncell;
 #pragma unroll
@@ -463,8 +531,9 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
         io.N[(size_t)g * nc + i] = (R)s.N[g];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            R &f = io.F[(size_t)(3 * g + d) * nc + i];
-            f = (R)((double)f * s.fs[g]);
+            const size_t j = (size_t)(3 * g + d) * nc + i;
+            R &f = io.F[j];
+            f = finish_flux(io, s, g, j, f);
         }
     }
     io.xHII[i] = s.x;

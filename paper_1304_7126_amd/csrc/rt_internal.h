@@ -58,8 +58,22 @@ constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
 size_t reduction_scratch_bytes();
 
+// prev (nsrc*M doubles, or null): receives each source cell's N before the
+// injection, for smoothed RT
 hipError_t launch_inject(bool fp32, void *N, size_t ncell, int M, int nsrc, const int32_t *cell,
-                         const double *rate, double dt_over_V, hipStream_t s);
+                         const double *rate, double dt_over_V, double *prev, hipStream_t s);
+
+// map[cell] = index of the source in that cell, -1 elsewhere
+hipError_t launch_source_map(int32_t *map, size_t ncell, const int32_t *cell, int nsrc, hipStream_t s);
+
+// Inputs of smoothed RT: the radiation set before injection and transport
+// (N, F), and for source cells their N before the injection (map, prev; map
+// null when no injection preceded the transport).
+struct SmoothArgs {
+    const void *N, *F;
+    const int32_t *map;
+    const double *prev;
+};
 
 // accounting partials: 6 doubles per transport block (sum of transported N
 // and of the outward boundary flux, per group), in caller scratch
@@ -83,9 +97,17 @@ struct QueueView {
     unsigned *count;  // [0] cells queued, [1] (head) cells taken by the tail
     unsigned *head;
     int32_t *cell, *acc, *att;
-    double *v;        // 18 planes of `stride` doubles
+    double *v;        // QV (smoothed RT: QV_SMOOTH) planes of `stride` doubles
     unsigned cap;     // cells the head pass may queue
     unsigned stride;  // plane length of the layout
+};
+
+template <typename R>
+struct SmoothIn {
+    const R *N = nullptr, *F = nullptr;  // radiation set before injection and transport
+    const int32_t *map = nullptr;        // source index per cell, or null
+    const double *prev = nullptr;        // N of each source cell before injection
+    double dt = 0.0;
 };
 
 template <typename R>
@@ -97,26 +119,29 @@ struct ChemIO {
     int32_t *nacc, *natt;
     double *acct;               // transport partials (fused head), or null
     unsigned long long *hist;   // substep histogram, or null
+    SmoothIn<R> sm;             // smoothed RT inputs (kernels instantiated for it)
 };
 
 constexpr int TAIL_BLOCKS = 1024;
 constexpr int HEAD_ATTEMPTS = 3;
 
-// bytes of scratch for a queue of cap cells (after the reduction partials)
-size_t queue_bytes(unsigned cap);
+// bytes of scratch for a queue of cap cells (after the reduction partials),
+// laid out for smoothed RT when smooth is set
+size_t queue_bytes(unsigned cap, bool smooth);
 // cap: cells the kernels may queue; layout_cap: capacity the scratch is laid out for
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
 
 // part 1: queue reset + head pass; part 2: tail pass
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
-                       const QueueView &q, int K, unsigned long long *hist, DevStats *stats, hipStream_t s);
+                       const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, DevStats *stats,
+                       hipStream_t s);
 
 hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, const KChem &kc, const KChem *dk, double dt, const void *Nin,
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
                              int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
-                             DevStats *stats, hipStream_t s);
+                             const SmoothArgs *sm, DevStats *stats, hipStream_t s);
 
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,

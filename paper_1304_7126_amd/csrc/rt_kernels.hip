@@ -17,28 +17,52 @@
 namespace rtm1 {
 
 // ------------------------------------------------------------------ inject
+// The source cells are distinct (sources sharing a cell are merged on the
+// host), so each thread owns its cell.  prev, when given, receives the
+// photon density before the injection (smoothed RT).
 template <typename R>
 __global__ void k_inject(R *__restrict__ N, size_t ncell, int M, int nsrc, const int32_t *__restrict__ cell,
-                         const double *__restrict__ rate, double dtV)
+                         const double *__restrict__ rate, double dtV, double *__restrict__ prev)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nsrc) return;
     const size_t i = (size_t)cell[s];
     for (int g = 0; g < M; ++g) {
         R *p = N + (size_t)g * ncell + i;
-        *p = R((double)*p + rate[(size_t)s * M + g] * dtV);
+        const double n0 = (double)*p;
+        if (prev) prev[(size_t)s * M + g] = n0;
+        *p = R(n0 + rate[(size_t)s * M + g] * dtV);
     }
 }
 
 hipError_t launch_inject(bool fp32, void *N, size_t ncell, int M, int nsrc, const int32_t *cell,
-                         const double *rate, double dt_over_V, hipStream_t s)
+                         const double *rate, double dt_over_V, double *prev, hipStream_t s)
 {
     if (nsrc <= 0) return hipSuccess;
     dim3 b(64), gr((nsrc + 63) / 64);
     if (fp32)
-        hipLaunchKernelGGL(k_inject<float>, gr, b, 0, s, (float *)N, ncell, M, nsrc, cell, rate, dt_over_V);
+        hipLaunchKernelGGL(k_inject<float>, gr, b, 0, s, (float *)N, ncell, M, nsrc, cell, rate, dt_over_V, prev);
     else
-        hipLaunchKernelGGL(k_inject<double>, gr, b, 0, s, (double *)N, ncell, M, nsrc, cell, rate, dt_over_V);
+        hipLaunchKernelGGL(k_inject<double>, gr, b, 0, s, (double *)N, ncell, M, nsrc, cell, rate, dt_over_V, prev);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t *p, size_t n, int32_t v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_source_map(int32_t *map, const int32_t *__restrict__ cell, int nsrc)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nsrc) map[cell[s]] = s;
+}
+
+hipError_t launch_source_map(int32_t *map, size_t ncell, const int32_t *cell, int nsrc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, map, ncell, -1);
+    if (nsrc > 0) hipLaunchKernelGGL(k_source_map, dim3((nsrc + 63) / 64), dim3(64), 0, s, map, cell, nsrc);
     return hipGetLastError();
 }
 
@@ -175,7 +199,9 @@ __device__ __forceinline__ void hist_flush(const unsigned *sh, unsigned long lon
 template <typename R, int M>
 constexpr int head_waves() { return (sizeof(R) == 4 || M < 3) ? 3 : 2; }
 
-template <typename R, int M, int FUSE, int FLUX>
+// With SM (smoothed RT) the chemistry starts from the radiation before
+// injection and transport (io.sm) and takes their change as a rate.
+template <typename R, int M, int FUSE, int FLUX, bool SM>
 __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, const KChem *__restrict__ kp, double dt, R c, R kdx, const R *__restrict__ Nin,
                                               const R *__restrict__ Fin, ChemIO<R> io, const R *__restrict__ tab,
                                               int nf, int nth, QueueView q, int K, DevStats *__restrict__ st)
@@ -184,7 +210,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < (uint32_t)g.ncell;
     const size_t nc = g.ncell;
-    CS s;
+    std::conditional_t<SM, CSR, CS> s;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool done = true;
     unsigned fl = 0;
@@ -195,6 +221,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
     for (int grp = 0; grp < CM; ++grp) {
         s.N[grp] = 0.0;
         s.fs[grp] = 1.0;
+        if constexpr (SM) s.Nr[grp] = 0.0;
     }
     if (valid) {
         bool fin = true;
@@ -225,13 +252,26 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
                 for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.F[(size_t)(3 * grp + d) * nc + i]);
             }
         }
+        if constexpr (SM) {
+            // N^t from the pre-step set, or for a source cell its value
+            // before the injection; rate (N' - N^t)/dt (eq. smoothrate1)
+            const int si = io.sm.map ? io.sm.map[i] : -1;
+#pragma unroll
+            for (int grp = 0; grp < M; ++grp) {
+                const double nt = si >= 0 ? io.sm.prev[(size_t)si * M + grp] : (double)io.sm.N[(size_t)grp * nc + i];
+                s.Nr[grp] = (s.N[grp] - nt) / dt;
+                s.N[grp] = nt;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.sm.F[(size_t)(3 * grp + d) * nc + i]);
+            }
+        }
         s.x = io.xHII[i];
         s.y2 = io.xHeII[i];
         s.y3 = io.xHeIII[i];
         cc = make_cc(k, io.nH[i], io.T[i]);
-        if (chem_init<CM>(k, dt, cc.Tiso, fin, s)) {
+        if (chem_init<CM, SM>(k, dt, cc.Tiso, fin, s)) {
             done = false;
-            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM>(k, cc, s, fl);
+            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM, SM>(k, cc, s, fl);
         } else {
             fl |= 2u;
         }
@@ -255,7 +295,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         }
     }
     if (want && !queued) {
-        while (!done) done = chem_attempt<CM>(k, cc, s, fl);
+        while (!done) done = chem_attempt<CM, SM>(k, cc, s, fl);
     }
     unsigned long long a_acc = 0, a_att = 0;
     if (valid && !queued) {
@@ -273,12 +313,12 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
 // cell, run one attempt per loop trip, and refill from the queue as soon as
 // their cell has filled dt_RT, so that a few slow cells do not hold whole
 // waves of finished lanes.
-template <typename R, int M>
+template <typename R, int M, bool SM>
 __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
     const unsigned n = min(*q.count, q.cap);
-    CS s;
+    std::conditional_t<SM, CSR, CS> s;
     uint32_t cell = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
@@ -308,7 +348,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
         }
         if (!__any(active)) break;
         if (active) {
-            if (chem_attempt<CM>(k, cc, s, fl)) {
+            if (chem_attempt<CM, SM>(k, cc, s, fl)) {
                 const double T = chem_finish<CM>(k, cc, s, fl);
                 store_cell<R, M>(io, cell, s, T);
                 if (io.hist) hist_add(s_hist, s.acc);
@@ -329,38 +369,54 @@ __global__ void k_zero_u32(unsigned *p, int n)
 }
 
 // part 1: reset the queue counters and run the head pass; part 2: the tail
-template <typename R, int M, int FUSE, int FLUX>
+template <typename R, int M, int FUSE, int FLUX, bool SM>
 static void launch_head_tail(int part, const KGrid &g, const KChem &kc, const KChem *dk, double dt, R c, R kdx, const void *Nin,
                              const void *Fin, const ChemIO<R> &io, const void *tab, int nf, int nth,
                              const QueueView &q, int K, DevStats *st, hipStream_t s)
 {
     if (part == 1) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 2);
-        hipLaunchKernelGGL((k_head<R, M, FUSE, FLUX>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g,
+        hipLaunchKernelGGL((k_head<R, M, FUSE, FLUX, SM>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g,
                            dk, dt, c, kdx, (const R *)Nin, (const R *)Fin, io, (const R *)tab, nf, nth, q, K, st);
     } else {
-        hipLaunchKernelGGL((k_tail<R, M>), dim3(TAIL_BLOCKS), dim3(256), 0, s, dk, io, q, st);
+        hipLaunchKernelGGL((k_tail<R, M, SM>), dim3(TAIL_BLOCKS), dim3(256), 0, s, dk, io, q, st);
     }
 }
 
-template <typename R, int FUSE, int FLUX>
+template <typename R, int FUSE, int FLUX, bool SM>
 static void dispatch_M(int part, const KGrid &g, const KChem &kc, const KChem *dk, double dt, R c, R kdx, const void *Nin, const void *Fin,
                        const ChemIO<R> &io, const void *tab, int nf, int nth, const QueueView &q, int K,
                        DevStats *st, hipStream_t s)
 {
-    if (kc.M == 1) launch_head_tail<R, 1, FUSE, FLUX>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
-    else if (kc.M == 2) launch_head_tail<R, 2, FUSE, FLUX>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
-    else launch_head_tail<R, 3, FUSE, FLUX>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    if (kc.M == 1) launch_head_tail<R, 1, FUSE, FLUX, SM>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else if (kc.M == 2) launch_head_tail<R, 2, FUSE, FLUX, SM>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else launch_head_tail<R, 3, FUSE, FLUX, SM>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+}
+
+template <typename R, int FUSE, int FLUX>
+static void dispatch_SM(int part, const KGrid &g, const KChem &kc, const KChem *dk, double dt, R c, R kdx, const void *Nin,
+                        const void *Fin, const ChemIO<R> &io, const void *tab, int nf, int nth, const QueueView &q,
+                        int K, DevStats *st, hipStream_t s)
+{
+    if (io.sm.N) dispatch_M<R, FUSE, FLUX, true>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else dispatch_M<R, FUSE, FLUX, false>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
 }
 
 template <typename R>
 static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *xHeII, double *xHeIII, double *T,
-                         const double *nH, int32_t *nacc, int32_t *natt, double *acct = nullptr,
-                         unsigned long long *hist = nullptr)
+                         const double *nH, int32_t *nacc, int32_t *natt, double *acct, unsigned long long *hist,
+                         const SmoothArgs *sm, double dt)
 {
     ChemIO<R> io;
     io.acct = acct;
     io.hist = hist;
+    if (sm) {
+        io.sm.N = (const R *)sm->N;
+        io.sm.F = (const R *)sm->F;
+        io.sm.map = sm->map;
+        io.sm.prev = sm->prev;
+        io.sm.dt = dt;
+    }
     io.ncell = ncell;
     io.N = (R *)N;
     io.F = (R *)F;
@@ -376,14 +432,15 @@ static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *x
 
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
-                       const QueueView &q, int K, unsigned long long *hist, DevStats *stats, hipStream_t s)
+                       const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, DevStats *stats,
+                       hipStream_t s)
 {
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist);
-        dispatch_M<float, 0, 0>(part, g, kc, dk, dt, 0.f, 0.f, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
+        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt);
+        dispatch_SM<float, 0, 0>(part, g, kc, dk, dt, 0.f, 0.f, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist);
-        dispatch_M<double, 0, 0>(part, g, kc, dk, dt, 0.0, 0.0, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
+        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt);
+        dispatch_SM<double, 0, 0>(part, g, kc, dk, dt, 0.0, 0.0, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     }
     return hipGetLastError();
 }
@@ -392,21 +449,21 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
                              int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
-                             DevStats *stats, hipStream_t s)
+                             const SmoothArgs *sm, DevStats *stats, hipStream_t s)
 {
     const double kdx = dt / g.dx;
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist);
+        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt);
         if (flux)
-            dispatch_M<float, 1, 1>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<float, 1, 1>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
-            dispatch_M<float, 1, 0>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<float, 1, 0>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist);
+        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt);
         if (flux)
-            dispatch_M<double, 1, 1>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<double, 1, 1>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
-            dispatch_M<double, 1, 0>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<double, 1, 0>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
     }
     return hipGetLastError();
 }
@@ -415,12 +472,12 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
 size_t reduction_scratch_bytes() { return (size_t)RED_BLOCKS * sizeof(RedOut); }
 
 // scratch layout: [reduction partials][2 counters, padded to 256 B]
-//                 [cell, acc, att: 3 x cap int32][18 x cap doubles]
+//                 [cell, acc, att: 3 x cap int32][QV (or QV_SMOOTH) x cap doubles]
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t queue_bytes(unsigned cap)
+size_t queue_bytes(unsigned cap, bool smooth)
 {
-    return 256 + align256((size_t)cap * 3 * sizeof(int32_t)) + (size_t)QV * cap * sizeof(double);
+    return 256 + align256((size_t)cap * 3 * sizeof(int32_t)) + (size_t)(smooth ? QV_SMOOTH : QV) * cap * sizeof(double);
 }
 
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)

@@ -58,7 +58,7 @@ class RTContext:
 
     def __init__(self, n, dx, bc, M, c_r, sigN, sigE, ebar, flux=0, isothermal=False, X=0.76, Y=0.24,
                  gamma=5.0 / 3.0, a_exp=1.0, x_min=1e-6, N_floor=0.0, max_attempts=100000, fp32=False,
-                 device="cuda", counters=False):
+                 device="cuda", counters=False, smooth=False):
         L = lib()
         g = capi.RtGrid()
         g.nx, g.ny, g.nz = (int(v) for v in n)
@@ -84,6 +84,7 @@ class RTContext:
         p.x_min = float(x_min)
         p.N_floor = float(N_floor)
         p.max_attempts = int(max_attempts)
+        p.smooth = int(bool(smooth))
         h = ctypes.c_void_p()
         rc = L.rt_init(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(p), ctypes.byref(h))
         check(rc, None)
@@ -93,6 +94,7 @@ class RTContext:
         self.dx = float(dx)
         self.c_r = float(c_r)
         self.fp32 = bool(fp32)
+        self.smooth = bool(smooth)
         self.device = torch.device(device)
         nx, ny, nz = self.n
         rdt = torch.float32 if fp32 else torch.float64

@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size: 256^3 x 3 groups in the launch
 configuration bench.py times (rt_step: injection, fused transport + first
-chemistry pass, compacted tail).  After some steps on the GPU the pre-step
+chemistry pass, compacted tail), plain and smoothed.  After some steps on the GPU the pre-step
 state is copied to the host, the oracle steps sampled cells one by one from
 it (or_step_cells), and the GPU's next rt_step is compared on those cells."""
 import numpy as np
@@ -21,12 +21,14 @@ def host_state(ctx):
             "xHeIII": ctx.xHeIII.cpu().numpy(), "T": ctx.T.cpu().numpy(), "nH": ctx.nH.cpu().numpy()}
 
 
-@pytest.mark.parametrize("fp32", [False, True])
-def test_256_cubed_sampled_cells_match_oracle(fp32):
+# smoothed RT (Sec. 4.4) runs with a photon floor of 1e-12 cm^-3
+@pytest.mark.parametrize("fp32,smooth", [(False, False), (True, False), (True, True)])
+def test_256_cubed_sampled_cells_match_oracle(fp32, smooth):
     assert torch.cuda.is_available()
     from paper_1304_7126_amd import RTContext
     w = ri.lognormal_256(steps=12)
-    ctx = RTContext.for_workload(w, fp32=fp32, counters=True)
+    floor = 1e-12 if smooth else 0.0
+    ctx = RTContext.for_workload(w, fp32=fp32, counters=True, smooth=smooth, N_floor=floor)
     ctx.load_state(ri.initial_state(w))
     ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
     ctx.set_sources(ijk, ctx.source_rates(nd))
@@ -37,8 +39,9 @@ def test_256_cubed_sampled_cells_match_oracle(fp32):
     ctx.step(dt, 1)
     g = ctx.state_numpy()
 
-    o = oracle.OracleRT.for_workload(w)
+    o = oracle.OracleRT.for_workload(w, N_floor=floor)
     assert o.courant_dt() == dt
+    N_pre = pre["N"].copy() if smooth else None
     o.inject(pre, dt, ijk, o.source_rates(nd))
     rng = np.random.default_rng(0)
     nc = w.ncell
@@ -46,7 +49,7 @@ def test_256_cubed_sampled_cells_match_oracle(fp32):
     heavy = np.argsort(natt_prev)[-1024:]
     cells = np.unique(np.concatenate([rng.integers(0, nc, 2048), heavy, src_cells, src_cells + 1,
                                       np.minimum(src_cells + w.n[0], nc - 1)]))
-    r = o.step_cells(pre, dt, cells)
+    r = o.step_cells(pre, dt, cells, N_pre=N_pre)
     M = w.spectrum.M
     gN = g["N"].reshape(M, -1)[:, cells].T
     gF = g["F"].reshape(M, 3, -1)[:, :, cells].transpose(2, 0, 1)
