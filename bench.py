@@ -29,9 +29,9 @@ VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 # 101-105), valid for the kernel sources they were taken with
 # (profiles/k_head_fused_256cube_3grp_pmc_bytes.md and _pmc_valu.md).
 KERNEL_SOURCES = ("rt_kernels.hip", "rt_cell.h", "rt_device.h", "rt_internal.h")
-COUNTERS_SOURCE_HASH = "361f64844e3b16d8"
-COUNTERS = {"read_bytes": 2641032 * 2 * 1024, "write_bytes": 3159520 * 1024, "valu_wave_instr": 3.314e9,
-            "lane_util": 0.676, "fp64_flops_all_lanes": 1.17e11, "ms": 5.864}
+COUNTERS_SOURCE_HASH = "242414a62d18fce1"
+COUNTERS = {"read_bytes": 2641281 * 2 * 1024, "write_bytes": 3159533 * 1024, "valu_wave_instr": 3.3145e9,
+            "lane_util": 0.676, "fp64_flops_all_lanes": 1.166e11, "ms": 5.839}
 
 
 def kernel_source_hash():
@@ -57,6 +57,11 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--form", choices=["grid", "batch", "adjoint"], default="grid",
                     help="grid: the 256^3 x 3 headline; batch: 64 uneven boxes, batched vs one-by-one")
+    ap.add_argument("--smooth", action="store_true", help="time the smoothed RT step (Sec. 4.4) instead")
+    ap.add_argument("--n-floor", type=float, default=None,
+                    help="photon density floor of the 10%% check (default 0; 1e-12 with --smooth)")
+    ap.add_argument("--smooth-steps", type=int, default=30,
+                    help="timed steps of the smoothed-vs-plain comparison at floor 1e-12 (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device 3 times "
                          "(reference kernel for HBM byte counters)")
@@ -99,6 +104,76 @@ def cpu_baseline(seconds, n_full, M):
     return {"value": cgu, "unit": "cell-group updates/s", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"{n}^3 x {M} groups lognormal box (same recipe and cell size), first {steps} RT steps "
                       f"from the initial state, {el:.1f} s wall"}
+
+
+def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, floor=0.0, nH_mean=1e-3):
+    """The lognormal n^3 x 3 workload: build it, run `warmup` steps, then time
+    `steps` rt_step calls (injection, transport fused with the first
+    chemistry pass, the compacted tail), with the library's HIP events
+    bracketing each kernel on its stream."""
+    import torch
+
+    import rt_inputs as ri
+    from paper_1304_7126_amd import RTContext
+    flux = ri.FLUX_HLL if flux_name == "hll" else ri.FLUX_GLF
+    w = ri.lognormal_box(n, 13.2 * n / 256, max(1, round(200 * (n / 256) ** 3)), steps=steps, seed=0, flux=flux)
+    w.nH_mean = nH_mean
+    M = w.spectrum.M
+    print(f"# building {n}^3 x {M} workload (mean n_H {nH_mean:g}, smooth={smooth}, N_floor={floor:g})",
+          file=sys.stderr, flush=True)
+    st = ri.initial_state(w)
+    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
+    ctx = RTContext.for_workload(w, fp32=fp32, smooth=smooth, N_floor=floor)
+    ctx.load_state(st)
+    ctx.set_sources(ijk, ctx.source_rates(nd))
+    dt = ctx.courant_dt()
+    if head_attempts > 0:
+        ctx.set_tuning(head_attempts, -1)
+    del st
+    print(f"# warmup {warmup} steps", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        ctx.step(dt, 1)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    ctx.set_timing(True)
+    ctx.timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(dt, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    s = ctx.stats()
+    per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tm.items()}
+    del ctx
+    return {"w": w, "M": M, "stats": s, "ms": wall * 1e3 / steps, "cgu": w.ncell * M * steps / wall, "per": per}
+
+
+def smoothing_comparison(n, fp32, flux_name, steps, warmup, head_attempts):
+    """Smoothed RT (Sec. 4.4) against plain operator splitting on the same
+    workload and photon floor (1e-12 cm^-3, far below the densities that
+    ionise: c_r sigma N dt ~ 1e-10 there): substeps and time per step, on
+    the headline's diffuse gas (mean n_H 1e-3 cm^-3) and on the same box
+    with 100 times denser gas, where the sources' photons are absorbed
+    within a step (the case the section describes)."""
+    out = {"N_floor": 1e-12, "timed_steps": steps, "warmup": warmup}
+    for name, nH in (("diffuse", 1e-3), ("dense", 1e-1)):
+        d = {"mean_nH": nH}
+        for smooth in (False, True):
+            r = grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth, 1e-12, nH)
+            s = r["stats"]
+            nc = r["w"].ncell
+            d["smoothed" if smooth else "plain"] = {
+                "value": r["cgu"], "unit": "cell-group updates/s", "ms_per_step": r["ms"],
+                "substeps_per_cell_step": s["substeps_total"] / (nc * steps),
+                "attempts_per_cell_step": s["attempts_total"] / (nc * steps), "attempts_max": s["attempts_max"],
+                "flags": s["flags"], "ms_per_launch": {k: r["per"][k] for k in ("inject", "head", "tail")}}
+        d["substep_ratio_plain_over_smoothed"] = (d["plain"]["substeps_per_cell_step"] /
+                                                  d["smoothed"]["substeps_per_cell_step"])
+        d["time_ratio_plain_over_smoothed"] = d["plain"]["ms_per_step"] / d["smoothed"]["ms_per_step"]
+        out[name] = d
+    return out
 
 
 def bench_batch(args):
@@ -224,53 +299,14 @@ def main():
                           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
                           "data": "synthetic", "config": {"workload": a["workload"]}, "adjoint": a}), flush=True)
         return
-    import numpy as np
     import torch
-
-    import rt_inputs as ri
-    from paper_1304_7126_amd import RTContext
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fp32 = not args.fp64
     n = args.n
-    flux = ri.FLUX_HLL if args.flux == "hll" else ri.FLUX_GLF
-    w = ri.lognormal_box(n, 13.2 * n / 256, max(1, round(200 * (n / 256) ** 3)), steps=args.steps, seed=0,
-                         flux=flux)
-    M = w.spectrum.M
-    print(f"# building {n}^3 x {M} workload", file=sys.stderr, flush=True)
-    st = ri.initial_state(w)
-    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
-    ctx = RTContext.for_workload(w, fp32=fp32)
-    ctx.load_state(st)
-    ctx.set_sources(ijk, ctx.source_rates(nd))
-    dt = ctx.courant_dt()
-    if args.head_attempts > 0:
-        ctx.set_tuning(args.head_attempts, -1)
-    del st
-
-    print(f"# warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ctx.step(dt, 1)
-    torch.cuda.synchronize()
-    ctx.reset_stats()
-
-    # timed region: rt_step, the production path (injection, then transport
-    # fused with the first chemistry pass, then the compacted tail), with
-    # the library's HIP events bracketing each kernel on its stream
-    K = args.steps
-    ctx.set_timing(True)
-    ctx.timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(dt, K)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    tm = ctx.timing()
-    ctx.set_timing(False)
-    s = ctx.stats()
-    ms = wall * 1e3 / K
-    cgu = w.ncell * M * K / wall
-    per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tm.items()}
+    floor = args.n_floor if args.n_floor is not None else (1e-12 if args.smooth else 0.0)
+    r = grid_run(n, fp32, args.flux, args.steps, args.warmup, args.head_attempts, args.smooth, floor)
+    w, M, K, s, ms, cgu, per = r["w"], r["M"], args.steps, r["stats"], r["ms"], r["cgu"], r["per"]
 
     rad, gas = algorithmic_bytes(M, fp32)
     step_bytes = w.ncell * (rad + gas)
@@ -279,7 +315,8 @@ def main():
     # algorithmic traffic; the tail re-touches only the queued cells
     t_head = per["head"]
     achieved = step_bytes / (t_head * 1e-3) / 1e9
-    counters_valid = kernel_source_hash() == COUNTERS_SOURCE_HASH and fp32 and n == 256 and args.flux == "hll"
+    counters_valid = (kernel_source_hash() == COUNTERS_SOURCE_HASH and fp32 and n == 256 and args.flux == "hll"
+                      and not args.smooth and floor == 0.0)
     traffic = COUNTERS["read_bytes"] + COUNTERS["write_bytes"] if counters_valid else None
     # the kernel is bound by its VALU issue rate: counter figures (static,
     # from the profile) and the live duration
@@ -297,6 +334,9 @@ def main():
             "ms_per_launch": {"inject": per["inject"], "head": per["head"], "tail": per["tail"]},
             "step_algorithmic_GBps": step_bytes / (ms * 1e-3) / 1e9,
             "step_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    wl = f"lognormal {n}^3 x {M} groups, 200 sources, {args.flux.upper()}, c_r=c/100"
+    if args.smooth or floor > 0:
+        wl += f"{', smoothed RT' if args.smooth else ''}, N_floor={floor:g}"
     out = {
         "metric": "RT cell-group updates/s at 256^3 x 3 groups; adjoint/forward cost ratio",
         "value": cgu,
@@ -310,16 +350,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 transport / f64 chemistry" if fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"lognormal {n}^3 x {M} groups, 200 sources, HLL, c_r=c/100",
+        "config": {"workload": wl,
                    "grid": [n, n, n], "groups": M, "flux": args.flux, "precision": "mixed" if fp32 else "fp64",
-                   "parallelism": "1 GPU"},
+                   "smooth": bool(args.smooth), "N_floor": floor, "parallelism": "1 GPU"},
         "chem": {"substeps_per_cell_step": s["substeps_total"] / (w.ncell * K),
                  "attempts_per_cell_step": s["attempts_total"] / (w.ncell * K),
                  "attempts_max": s["attempts_max"], "flags": s["flags"]},
         "roofline": roof,
     }
-    del ctx
     torch.cuda.empty_cache()
+    if args.smooth_steps > 0 and not args.smooth:
+        out["smoothing"] = smoothing_comparison(n, fp32, args.flux, args.smooth_steps, args.warmup,
+                                                args.head_attempts)
+        torch.cuda.empty_cache()
     if not args.no_adjoint:
         print("# adjoint cost (64^3 differentiation workload)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_cost()
