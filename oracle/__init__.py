@@ -88,6 +88,7 @@ class OrParams(ctypes.Structure):
         ("max_attempts", ctypes.c_longlong),
         ("hll", ctypes.POINTER(ctypes.c_double)),
         ("hll_nf", ctypes.c_int), ("hll_nth", ctypes.c_int),
+        ("brec", ctypes.c_int * 3),
     ]
 
 
@@ -135,7 +136,7 @@ class OracleRT:
 
     def __init__(self, n, dx, bc, M, c_r, sigN, sigE, ebar, flux=0, otsa=True,
                  isothermal=False, X=0.76, Y=0.24, gamma=5.0 / 3.0, a_exp=1.0, x_min=1e-6,
-                 N_floor=0.0, max_attempts=100000, hll=None):
+                 N_floor=0.0, max_attempts=100000, hll=None, brec=(-1, -1, -1)):
         p = OrParams()
         p.nx, p.ny, p.nz = (int(v) for v in n)
         p.dx = float(dx)
@@ -157,6 +158,8 @@ class OracleRT:
         p.x_min = float(x_min)
         p.N_floor = float(N_floor)
         p.max_attempts = int(max_attempts)
+        for j in range(3):
+            p.brec[j] = int(brec[j])
         self._hll = np.ascontiguousarray(hll if hll is not None else hll_table(), dtype=np.float64)
         p.hll = _dp(self._hll)
         p.hll_nf, p.hll_nth = self._hll.shape[0], self._hll.shape[1]
@@ -171,7 +174,7 @@ class OracleRT:
         sigN, sigE, ebar, frac = physics.spectrum_attributes(w.spectrum)
         kw = dict(n=w.n, dx=w.dx, bc=w.bc, M=w.spectrum.M, c_r=w.c_r, sigN=sigN, sigE=sigE,
                   ebar=ebar, flux=w.flux, otsa=w.otsa, isothermal=w.isothermal, X=w.X, Y=w.Y,
-                  gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min)
+                  gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min, brec=w.brec)
         kw.update(over)
         o = cls(**kw)
         o.group_frac = frac[: w.spectrum.M].copy()

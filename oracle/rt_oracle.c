@@ -65,6 +65,9 @@ typedef struct {
     long long max_attempts;    /* cap on chemistry attempts per cell per RT step */
     const double *hll;         /* [nf][nth][2] (lambda_min, lambda_max), c = 1 */
     int hll_nf, hll_nth;
+    int brec[3];               /* without OTSA: the group receiving the recombination
+                                * photons of HII, HeII, HeIII (b^rec of eq. cool_N_cr),
+                                * -1: none */
 } or_params;
 
 /* ======================================================================
@@ -570,10 +573,24 @@ unsigned or_thermo_cell_rates(const or_params *p, double dtRT, double nH, double
         const double nHII = x * nH;
         const double nHeIII = y3 * nHe;
         double Nn[3], Fn[3][3];
+        /* photons from recombinations straight to the ground state, eq.
+         * cool_N_cr, without OTSA (Sec. 3.3.2): (alpha_A - alpha_B) n_j n_e
+         * with the state at the start of the substep */
+        double Crec[3] = {0.0, 0.0, 0.0};
+        if (!p->otsa) {
+            const double Tc = p->isothermal ? Tiso : Tmu * mu_of(p, x, y2, y3);
+            const double ne = nHII + (y2 + 2.0 * y3) * nHe;
+            const double em[3] = {(or_alphaA_HII(Tc).v - or_alphaB_HII(Tc).v) * nHII * ne,
+                                  (or_alphaA_HeII(Tc).v - or_alphaB_HeII(Tc).v) * nHeII * ne,
+                                  (or_alphaA_HeIII(Tc).v - or_alphaB_HeIII(Tc).v) * nHeIII * ne};
+            for (int j = 0; j < 3; j++)
+                if (p->brec[j] >= 0 && p->brec[j] < M) Crec[p->brec[j]] += em[j];
+        }
         for (int g = 0; g < M; g++) {
             double D = cr * (p->sigN[g][0] * nHI + p->sigN[g][1] * nHeI + p->sigN[g][2] * nHeII);
-            /* eq. SIE photons, with the smoothed-RT rates when given */
-            Nn[g] = (Nr ? N[g] + h * Nr[g] : N[g]) / (1.0 + h * D);
+            /* eq. SIE photons: creation by recombinations and, with
+             * smoothing, the transport rate */
+            Nn[g] = (N[g] + h * (Crec[g] + (Nr ? Nr[g] : 0.0))) / (1.0 + h * D);
             /* a negative rate can take the smoothed update below zero (its
              * steady state Nr/D is then negative): no photon density is
              * negative, so it stops at zero.  Above N_floor the 10% check

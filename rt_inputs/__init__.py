@@ -54,6 +54,33 @@ class Spectrum:
         return len(self.edges_eV) - 1
 
 
+# ionisation energies [eV] of the species whose recombinations to the ground
+# state emit ionising photons: HII (-> HI), HeII (-> HeI), HeIII (-> HeII)
+RECOMBINING_THRESHOLDS_EV = (13.60, 24.59, 54.42)
+
+
+def recombination_groups(spec: "Spectrum") -> tuple:
+    """For each of HII, HeII, HeIII the photon group its recombination
+    photons go to (just above the threshold): the blackbody group whose
+    energy interval holds the threshold, or the monochromatic group of the
+    lowest energy at or above it; -1 where there is none."""
+    out = []
+    for e in RECOMBINING_THRESHOLDS_EV:
+        g = -1
+        if spec.kind == "mono":
+            best = None
+            for i, ei in enumerate(spec.mono_energy_eV):
+                if ei >= e - 1e-9 and (best is None or ei < best):
+                    best, g = ei, i
+        else:
+            ed = spec.edges_eV
+            for i in range(len(ed) - 1):
+                if ed[i] - 1e-9 <= e < ed[i + 1] - 1e-9:
+                    g = i
+        out.append(g)
+    return tuple(out)
+
+
 @dataclasses.dataclass
 class Workload:
     name: str
@@ -84,6 +111,10 @@ class Workload:
     @property
     def dx(self) -> float:
         return self.L / self.n[0]
+
+    @property
+    def brec(self) -> tuple:
+        return recombination_groups(self.spectrum)
 
     @property
     def ncell(self) -> int:
