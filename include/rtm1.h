@@ -75,19 +75,28 @@ typedef struct {
 /* Photon groups (Sec. 2): M in 1..3; reduced light speed c_r [cm/s];
  * group-averaged cross sections sigN (eq. csn_multi) and energy-weighted
  * cross sections sigE (eq. cse_multi) [cm^2], indexed [group][HI,HeI,HeII];
- * mean photon energies ebar (eq. egy_multi) [erg].  Rows >= M are ignored. */
+ * mean photon energies ebar (eq. egy_multi) [erg].  Rows >= M are ignored.
+ * brec[j]: the group that receives the photons of recombinations straight to
+ * the ground state of HII, HeII, HeIII (j = 0, 1, 2; the b^rec of eq.
+ * cool_N_cr), normally the group holding the species' ionisation threshold;
+ * -1: none.  Read only with otsa = 0. */
 typedef struct {
     int M;
     double c_r;
     double sigN[3][3];
     double sigE[3][3];
     double ebar[3];
+    int brec[3];
 } rt_groups;
 
 /* Method options.
  *   flux        RT_FLUX_GLF (eq. glf) or RT_FLUX_HLL (eq. hll)
- *   otsa        on-the-spot approximation (Sec. 3.3.2): case-B rates, no
- *               recombination photons; only otsa = 1 is supported
+ *   otsa        on-the-spot approximation (Sec. 3.3.2): 1 = case-B rates, no
+ *               recombination photons; 0 = case-A recombination rates and
+ *               recombination cooling, and the photons of recombinations
+ *               straight to the ground state, (alpha_A - alpha_B) n_j n_e
+ *               with the state at the start of each substep, added to group
+ *               brec[j] (eq. cool_N_cr).  The batch and the adjoint need 1.
  *   isothermal  hold T fixed in the thermochemistry (no thermal update)
  *   prec        RT_PREC_FP64 or RT_PREC_FP32_TRANSPORT
  *   X, Y        hydrogen and helium mass fractions (X > 0, Y >= 0)

@@ -49,7 +49,7 @@ class RTBatch:
 
     def __init__(self, grids, groups, flux=0, isothermal=False, X=0.76, Y=0.24, gamma=5.0 / 3.0, a_exp=1.0,
                  x_min=1e-6, N_floor=0.0, max_attempts=100000, fp32=False, device="cuda", counters=False,
-                 smooth=False):
+                 smooth=False, otsa=True):
         L = lib()
         nb = len(grids)
         cg = (capi.RtGrid * nb)()
@@ -66,7 +66,7 @@ class RTBatch:
                     cr[i].sigE[a][j] = float(sE[a][j])
                 cr[i].ebar[a] = float(eb[a])
         p = capi.RtParams()
-        p.flux, p.otsa, p.isothermal = int(flux), 1, int(bool(isothermal))
+        p.flux, p.otsa, p.isothermal = int(flux), int(bool(otsa)), int(bool(isothermal))
         p.prec = capi.RT_PREC_FP32_TRANSPORT if fp32 else capi.RT_PREC_FP64
         p.X, p.Y, p.gamma, p.a_exp = float(X), float(Y), float(gamma), float(a_exp)
         p.x_min, p.N_floor, p.max_attempts = float(x_min), float(N_floor), int(max_attempts)

@@ -37,7 +37,7 @@ class RtGrid(ctypes.Structure):
 class RtGroups(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int), ("c_r", ctypes.c_double),
                 ("sigN", (ctypes.c_double * 3) * 3), ("sigE", (ctypes.c_double * 3) * 3),
-                ("ebar", ctypes.c_double * 3)]
+                ("ebar", ctypes.c_double * 3), ("brec", ctypes.c_int * 3)]
 
 
 class RtParams(ctypes.Structure):

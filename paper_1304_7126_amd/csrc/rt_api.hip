@@ -337,7 +337,14 @@ static rt_status validate(const rt_grid *g, const rt_groups *gr, const rt_params
             if (!(gr->sigN[i][j] >= 0) || !(gr->sigE[i][j] >= 0)) { err = "cross sections must be >= 0"; return RT_EINVAL; }
     }
     if (p->flux != RT_FLUX_GLF && p->flux != RT_FLUX_HLL) { err = "flux must be GLF or HLL"; return RT_EINVAL; }
-    if (p->otsa != 1) { err = "only the on-the-spot approximation (otsa = 1) is supported"; return RT_EUNSUPPORTED; }
+    if (p->otsa != 0 && p->otsa != 1) { err = "otsa must be 0 or 1"; return RT_EINVAL; }
+    if (!p->otsa)
+        for (int j = 0; j < 3; ++j)
+            if (gr->brec[j] < -1 || gr->brec[j] >= gr->M) {
+                snprintf(b, sizeof b, "brec[%d] must be -1 or a group index below M", j);
+                err = b;
+                return RT_EINVAL;
+            }
     if (p->prec != RT_PREC_FP64 && p->prec != RT_PREC_FP32_TRANSPORT) { err = "prec invalid"; return RT_EINVAL; }
     if (!(p->X > 0) || !(p->Y >= 0) || p->X + p->Y > 1.0 + 1e-12) { err = "need X > 0, Y >= 0, X + Y <= 1"; return RT_EINVAL; }
     if (!(p->gamma > 1)) { err = "gamma must be > 1"; return RT_EINVAL; }
@@ -387,6 +394,9 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     k.x_min = params->x_min;
     k.N_floor = params->N_floor;
     k.max_att = params->max_attempts;
+    k.otsa = params->otsa;
+    for (int g = 0; g < 3; ++g)
+        for (int j = 0; j < 3; ++j) k.brec[g][j] = (!params->otsa && groups->brec[j] == g) ? 1.0 : 0.0;
     kchem_derive(k);
 
     build_hll(c->nf, c->nth, c->hll_host);
@@ -843,6 +853,7 @@ static rt_status adj_supported(rt_ctx *c, double dt)
     if (c->params.flux != RT_FLUX_GLF) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the GLF flux");
     if (c->fp32) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs RT_PREC_FP64");
     if (c->params.smooth) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs smooth = 0");
+    if (!c->params.otsa) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the on-the-spot approximation (otsa = 1)");
     for (int f = 0; f < 6; ++f)
         if (c->grid.bc[f] != RT_BC_PERIODIC) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs periodic boundaries");
     const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);

@@ -450,7 +450,7 @@ extern "C" rt_status rt_batch_init(int nbox, const rt_grid *grids, const rt_grou
         return RT_EUNSUPPORTED;
     }
     if (params->otsa != 1) {
-        g_batch_err = "only the on-the-spot approximation (otsa = 1) is supported";
+        g_batch_err = "the batch runs with the on-the-spot approximation (otsa = 1)";
         return RT_EUNSUPPORTED;
     }
     if (params->flux != RT_FLUX_GLF && params->flux != RT_FLUX_HLL) { g_batch_err = "flux invalid"; return RT_EINVAL; }

@@ -237,9 +237,16 @@ __device__ __forceinline__ CC make_cc(const KChem &k, double nH, double T)
 
 // Returns false (and leaves the cell untouched) when an input is not finite;
 // fin says whether the cell's fluxes are finite.
-template <int M, bool SM = false, class St>
+// Method variant of the chemistry kernels: bit 0 smoothed RT (Sec. 4.4),
+// bit 1 no on-the-spot approximation (Sec. 3.3.2: case A rates and the
+// photons of recombinations to the ground state).
+constexpr int V_SMOOTH = 1;
+constexpr int V_CASE_A = 2;
+
+template <int M, int V = 0, class St>
 __device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, bool fin, St &s)
 {
+    constexpr bool SM = (V & V_SMOOTH) != 0;
     bool ok = fin && isfinite(T) && isfinite(s.x) && isfinite(s.y2) && isfinite(s.y3);
 #pragma unroll
     for (int g = 0; g < M; ++g) {
@@ -263,9 +270,11 @@ __device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, b
 // advances by h, and the next h doubles when every relative change was
 // below 5%.  Returns true when the cell has filled dt_RT (or reached the
 // attempt cap, flag bit 0).
-template <int M, bool SM = false, class St>
+template <int M, int V = 0, class St>
 __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s, unsigned &flags)
 {
+    constexpr bool SM = (V & V_SMOOTH) != 0;
+    constexpr bool CA = (V & V_CASE_A) != 0;
     if (s.att >= k.max_att) {
         flags |= 1u;
         return true;
@@ -285,14 +294,30 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
     const double nHeIII = y3 * nHe;
     double Nn[M], rd[M];
     bool fail = false;
+    // without OTSA: photons of recombinations straight to the ground state,
+    // (alpha_A - alpha_B) n_j n_e with the state at the start of the
+    // substep, into the group that holds species j's threshold (eq. cool_N_cr)
+    double Crec[M];
+    if constexpr (CA) {
+        const Tq qc = make_Tq(iso ? cc.Tiso : Tmu * mu_of(k, x, y2, y3));
+        const double ne = nHII + (y2 + 2.0 * y3) * nHe;
+        const double em0 = (alphaA_HII(qc).v - alphaB_HII(qc).v) * nHII * ne;
+        const double em1 = (alphaA_HeII(qc).v - alphaB_HeII(qc).v) * nHeII * ne;
+        const double em2 = (alphaA_HeIII(qc).v - alphaB_HeIII(qc).v) * nHeIII * ne;
+#pragma unroll
+        for (int g = 0; g < M; ++g) Crec[g] = k.brec[g][0] * em0 + k.brec[g][1] * em1 + k.brec[g][2] * em2;
+    }
 #pragma unroll
     for (int g = 0; g < M; ++g) {
         const double D = k.csN[g][0] * nHI + k.csN[g][1] * nHeI + k.csN[g][2] * nHeII;
         rd[g] = 1.0 / (1.0 + h * D);
         if constexpr (SM) {
             // a negative rate may take the update below zero: it stops there
-            const double nn = (s.N[g] + h * s.Nr[g]) * rd[g];
+            const double src = CA ? Crec[g] + s.Nr[g] : s.Nr[g];
+            const double nn = (s.N[g] + h * src) * rd[g];
             Nn[g] = nn < 0.0 ? 0.0 : nn;
+        } else if constexpr (CA) {
+            Nn[g] = (s.N[g] + h * Crec[g]) * rd[g];
         } else
             Nn[g] = s.N[g] * rd[g];
         if (s.N[g] > k.N_floor) {
@@ -322,7 +347,7 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
             }
         }
         double L, dL;
-        cooling_B(q0, k.a_exp, ne0, nHI, nHII, nHeI, nHeII, nHeIII, L, dL);
+        cooling<CA>(q0, k.a_exp, ne0, nHI, nHII, nHeI, nHeII, nHeIII, L, dL);
         const double Lam = H - L;
         const double Lamp = -mu0 * dL;
         const double den = 1.0 - Lamp * K * h;
@@ -347,7 +372,7 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
     }
     const Tq q1 = make_Tq(iso ? cc.Tiso : Tmun * mu0);
     const vd bH = beta_HI(q1);
-    const vd aH = alphaB_HII(q1);
+    const vd aH = alpha_HII<CA>(q1);
     const double Cr = bH.v * ne0 + GHI;
     const double Dr = aH.v * ne0;
     double dC, dD;
@@ -378,14 +403,14 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
     if (nHe > 0.0) {
         const double ne1 = xn * nH + (y2 + 2.0 * y3) * nHe;
         const Tq q2 = make_Tq(iso ? cc.Tiso : Tmun * mu_of(k, xn, y2, y3));
-        const vd bHe1 = beta_HeI(q2), aHe2 = alphaB_HeII(q2), bHe2 = beta_HeII(q2), aHe3 = alphaB_HeIII(q2);
+        const vd bHe1 = beta_HeI(q2), aHe2 = alpha_HeII<CA>(q2), bHe2 = beta_HeII(q2), aHe3 = alpha_HeIII<CA>(q2);
         const double y1 = 1.0 - y2 - y3;
         const double y1n = (y1 + y2 * aHe2.v * ne1 * h) / (1.0 + (bHe1.v * ne1 + GHeI) * h);
         y2n = (y2 + (y1n * (bHe1.v * ne1 + GHeI) + y3 * aHe3.v * ne1) * h) /
               (1.0 + ((bHe2.v + aHe2.v) * ne1 + GHeII) * h);
         const double ne2 = xn * nH + (y2n + 2.0 * y3) * nHe;
         const Tq q3 = make_Tq(iso ? cc.Tiso : Tmun * mu_of(k, xn, y2n, y3));
-        const vd bHe2b = beta_HeII(q3), aHe3b = alphaB_HeIII(q3);
+        const vd bHe2b = beta_HeII(q3), aHe3b = alpha_HeIII<CA>(q3);
         y3n = (y3 + y2n * (bHe2b.v * ne2 + GHeII) * h) / (1.0 + aHe3b.v * ne2 * h);
         const double S = y1n + y2n + y3n;
         if (!(y1n >= y2n && y1n >= y3n)) {

@@ -130,8 +130,8 @@ __device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, in
 }
 
 // ---------------------------------------------------------------------
-// App. E rate coefficients (case B: the library runs with the on-the-spot
-// approximation of Sec. 3.3.2).  vd holds value v and derivative d = dv/dT.
+// App. E rate coefficients, case B (on-the-spot approximation, Sec. 3.3.2)
+// and case A (without it).  vd holds value v and derivative d = dv/dT.
 // ---------------------------------------------------------------------
 struct vd {
     double v, d;
@@ -220,17 +220,40 @@ __device__ __forceinline__ vd alphaB_HeIII(const Tq &q)
     return r_hg(q, 5.506e-14, LN_TL_HEII, 1.5, LN_2p74, 0.407, 2.242);
 }
 
-// (lambda_HeII / lambda_HI)^0.376 = (1263030 / 315614)^0.376: the ratio of
-// the Hui & Gnedin terms (lambda/2.25)^0.376 of the HeIII and HII
-// recombination-cooling fits at one temperature
-constexpr double HG_COOL_U_RATIO = 1.6844137772424854;
+// case A (E.2): recombinations to every level
+constexpr double LN_0p522 = -0.6500876910994983;
+constexpr double LN_0p541 = -0.6143360001356555;
+__device__ __forceinline__ vd alphaA_HII(const Tq &q)
+{
+    return r_hg(q, 1.269e-13, LN_TL_HI, 1.503, LN_0p522, 0.47, 1.923);
+}
+__device__ __forceinline__ vd alphaA_HeII(const Tq &q) { return r_pw(q, 3e-14, LN_TL_HEI, 0.654); }
+__device__ __forceinline__ vd alphaA_HeIII(const Tq &q)
+{
+    return r_hg(q, 2.538e-13, LN_TL_HEII, 1.503, LN_0p522, 0.47, 1.923);
+}
 
-// Primordial cooling L of eq. (rate_cooling), case B (OTSA), and dL/dT.
-// Products of exponentials are taken as one exponential of the summed
-// arguments, and the HeIII recombination term reuses the HII term's
-// (lambda/l0)^q.
-__device__ __forceinline__ void cooling_B(const Tq &q, double a_exp, double ne, double nHI, double nHII,
-                                          double nHeI, double nHeII, double nHeIII, double &L, double &dL)
+// the recombination rates of the case in use: CA = case A (no OTSA)
+template <bool CA>
+__device__ __forceinline__ vd alpha_HII(const Tq &q) { return CA ? alphaA_HII(q) : alphaB_HII(q); }
+template <bool CA>
+__device__ __forceinline__ vd alpha_HeII(const Tq &q) { return CA ? alphaA_HeII(q) : alphaB_HeII(q); }
+template <bool CA>
+__device__ __forceinline__ vd alpha_HeIII(const Tq &q) { return CA ? alphaA_HeIII(q) : alphaB_HeIII(q); }
+
+// (lambda_HeII / lambda_HI)^q = (1263030 / 315614)^q: the ratio of the Hui &
+// Gnedin terms (lambda/l0)^q of the HeIII and HII recombination-cooling fits
+// at one temperature, for the case B (q = 0.376) and case A (q = 0.502) fits
+constexpr double HG_COOL_U_RATIO = 1.6844137772424854;
+constexpr double HG_COOL_U_RATIO_A = 2.006010575388344;
+
+// Primordial cooling L of eq. (rate_cooling) and dL/dT, with the case B
+// recombination cooling of the OTSA or (CA) the case A one.  Products of
+// exponentials are taken as one exponential of the summed arguments, and the
+// HeIII recombination term reuses the HII term's (lambda/l0)^q.
+template <bool CA>
+__device__ __forceinline__ void cooling(const Tq &q, double a_exp, double ne, double nHI, double nHII,
+                                        double nHeI, double nHeII, double nHeIII, double &L, double &dL)
 {
     const double sqT = q.sqT;
     // collisional ionisation cooling (Cen form), three species
@@ -247,21 +270,26 @@ __device__ __forceinline__ void cooling_B(const Tq &q, double a_exp, double ne, 
     const double psHI = 7.5e-19 * q.g * exp(-118348.0 * q.invT), psHIl = gdl + 118348.0 * q.invT;
     const double psHeII = 5.54e-17 * q.g * exp(-0.397 * q.lnT - 473638.0 * q.invT);
     const double psHeIIl = -0.397 + gdl + 473638.0 * q.invT;
-    // recombination cooling, case B: B T lam^p / (1 + (lam/l0)^q)^r for HII
+    // recombination cooling: B T lam^p / (1 + (lam/l0)^q)^r for HII
     // (lam = 315614/T) and HeIII (lam = 1263030/T, 8 B)
     vd eHII, eHeIII;
     {
-        constexpr double p = 1.97, qq = 0.376, r = 3.72;
+        constexpr double B = CA ? 1.778e-29 : 3.435e-30;
+        constexpr double p = CA ? 1.965 : 1.97, qq = CA ? 0.502 : 0.376, r = CA ? 2.697 : 3.72;
+        constexpr double lnl0 = CA ? LN_0p541 : LN_2p25;
+        constexpr double ratio = CA ? HG_COOL_U_RATIO_A : HG_COOL_U_RATIO;
         const double l1 = LN_TL_HI - q.lnT, l3 = LN_TL_HEII - q.lnT;
-        const double u1 = exp(qq * (l1 - LN_2p25));
-        const double u3 = u1 * HG_COOL_U_RATIO;
-        eHII.v = 3.435e-30 * q.T * exp(p * l1 - r * log1p(u1));
-        eHeIII.v = 8.0 * 3.435e-30 * q.T * exp(p * l3 - r * log1p(u3));
+        const double u1 = exp(qq * (l1 - lnl0));
+        const double u3 = u1 * ratio;
+        eHII.v = B * q.T * exp(p * l1 - r * log1p(u1));
+        eHeIII.v = 8.0 * B * q.T * exp(p * l3 - r * log1p(u3));
         eHII.d = eHII.v * (1.0 - (p - r * qq * u1 / (1.0 + u1))) * q.invT;
         eHeIII.d = eHeIII.v * (1.0 - (p - r * qq * u3 / (1.0 + u3))) * q.invT;
     }
-    const vd aB2 = r_pw(q, 1.26e-14, LN_TL_HEI, 0.75);
-    const double eHeII = KB * q.T * aB2.v, eHeIIl = 1.0 - 0.75;
+    // eta_HeII = k_B T alpha_HeII
+    constexpr double pHe2 = CA ? 0.654 : 0.75;
+    const vd aHe2 = r_pw(q, CA ? 3e-14 : 1.26e-14, LN_TL_HEI, pHe2);
+    const double eHeII = KB * q.T * aHe2.v, eHeIIl = 1.0 - pHe2;
     // dielectronic recombination
     const double ed2 = exp(-94000.0 * q.invT);
     const double om = 1.24e-13 * exp(-1.5 * q.lnT - 470000.0 * q.invT) * (1.0 + 0.3 * ed2);

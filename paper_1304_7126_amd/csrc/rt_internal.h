@@ -30,6 +30,8 @@ struct KChem {
     double x_min;
     double N_floor;
     long long max_att;
+    int otsa;           // 1: on-the-spot approximation; 0: case A with recombination photons
+    double brec[3][3];  // [group][HII, HeII, HeIII]: 1 where the species' recombination photons go
 };
 
 // device statistics block (in library memory)

@@ -199,9 +199,10 @@ __device__ __forceinline__ void hist_flush(const unsigned *sh, unsigned long lon
 template <typename R, int M>
 constexpr int head_waves() { return (sizeof(R) == 4 || M < 3) ? 3 : 2; }
 
-// With SM (smoothed RT) the chemistry starts from the radiation before
-// injection and transport (io.sm) and takes their change as a rate.
-template <typename R, int M, int FUSE, int FLUX, bool SM>
+// V selects the method variant of the chemistry (V_SMOOTH: it starts from
+// the radiation before injection and transport, io.sm, and takes their
+// change as a rate; V_CASE_A: no on-the-spot approximation).
+template <typename R, int M, int FUSE, int FLUX, int V>
 __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, const KChem *__restrict__ kp, double dt, R c, R kdx, const R *__restrict__ Nin,
                                               const R *__restrict__ Fin, ChemIO<R> io, const R *__restrict__ tab,
                                               int nf, int nth, QueueView q, int K, DevStats *__restrict__ st)
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < (uint32_t)g.ncell;
     const size_t nc = g.ncell;
+    constexpr bool SM = (V & V_SMOOTH) != 0;
     std::conditional_t<SM, CSR, CS> s;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool done = true;
@@ -269,9 +271,9 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         s.y2 = io.xHeII[i];
         s.y3 = io.xHeIII[i];
         cc = make_cc(k, io.nH[i], io.T[i]);
-        if (chem_init<CM, SM>(k, dt, cc.Tiso, fin, s)) {
+        if (chem_init<CM, V>(k, dt, cc.Tiso, fin, s)) {
             done = false;
-            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM, SM>(k, cc, s, fl);
+            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM, V>(k, cc, s, fl);
         } else {
             fl |= 2u;
         }
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         }
     }
     if (want && !queued) {
-        while (!done) done = chem_attempt<CM, SM>(k, cc, s, fl);
+        while (!done) done = chem_attempt<CM, V>(k, cc, s, fl);
     }
     unsigned long long a_acc = 0, a_att = 0;
     if (valid && !queued) {
@@ -313,12 +315,12 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
 // cell, run one attempt per loop trip, and refill from the queue as soon as
 // their cell has filled dt_RT, so that a few slow cells do not hold whole
 // waves of finished lanes.
-template <typename R, int M, bool SM>
+template <typename R, int M, int V>
 __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
     const unsigned n = min(*q.count, q.cap);
-    std::conditional_t<SM, CSR, CS> s;
+    std::conditional_t<(V & V_SMOOTH) != 0, CSR, CS> s;
     uint32_t cell = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
         }
         if (!__any(active)) break;
         if (active) {
-            if (chem_attempt<CM, SM>(k, cc, s, fl)) {
+            if (chem_attempt<CM, V>(k, cc, s, fl)) {
                 const double T = chem_finish<CM>(k, cc, s, fl);
                 store_cell<R, M>(io, cell, s, T);
                 if (io.hist) hist_add(s_hist, s.acc);
@@ -369,28 +371,28 @@ __global__ void k_zero_u32(unsigned *p, int n)
 }
 
 // part 1: reset the queue counters and run the head pass; part 2: the tail
-template <typename R, int M, int FUSE, int FLUX, bool SM>
+template <typename R, int M, int FUSE, int FLUX, int V>
 static void launch_head_tail(int part, const KGrid &g, const KChem &kc, const KChem *dk, double dt, R c, R kdx, const void *Nin,
                              const void *Fin, const ChemIO<R> &io, const void *tab, int nf, int nth,
                              const QueueView &q, int K, DevStats *st, hipStream_t s)
 {
     if (part == 1) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 2);
-        hipLaunchKernelGGL((k_head<R, M, FUSE, FLUX, SM>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g,
+        hipLaunchKernelGGL((k_head<R, M, FUSE, FLUX, V>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g,
                            dk, dt, c, kdx, (const R *)Nin, (const R *)Fin, io, (const R *)tab, nf, nth, q, K, st);
     } else {
-        hipLaunchKernelGGL((k_tail<R, M, SM>), dim3(TAIL_BLOCKS), dim3(256), 0, s, dk, io, q, st);
+        hipLaunchKernelGGL((k_tail<R, M, V>), dim3(TAIL_BLOCKS), dim3(256), 0, s, dk, io, q, st);
     }
 }
 
-template <typename R, int FUSE, int FLUX, bool SM>
+template <typename R, int FUSE, int FLUX, int V>
 static void dispatch_M(int part, const KGrid &g, const KChem &kc, const KChem *dk, double dt, R c, R kdx, const void *Nin, const void *Fin,
                        const ChemIO<R> &io, const void *tab, int nf, int nth, const QueueView &q, int K,
                        DevStats *st, hipStream_t s)
 {
-    if (kc.M == 1) launch_head_tail<R, 1, FUSE, FLUX, SM>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
-    else if (kc.M == 2) launch_head_tail<R, 2, FUSE, FLUX, SM>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
-    else launch_head_tail<R, 3, FUSE, FLUX, SM>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    if (kc.M == 1) launch_head_tail<R, 1, FUSE, FLUX, V>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else if (kc.M == 2) launch_head_tail<R, 2, FUSE, FLUX, V>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else launch_head_tail<R, 3, FUSE, FLUX, V>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
 }
 
 template <typename R, int FUSE, int FLUX>
@@ -398,8 +400,11 @@ static void dispatch_SM(int part, const KGrid &g, const KChem &kc, const KChem *
                         const void *Fin, const ChemIO<R> &io, const void *tab, int nf, int nth, const QueueView &q,
                         int K, DevStats *st, hipStream_t s)
 {
-    if (io.sm.N) dispatch_M<R, FUSE, FLUX, true>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
-    else dispatch_M<R, FUSE, FLUX, false>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    const int v = (io.sm.N ? V_SMOOTH : 0) | (kc.otsa ? 0 : V_CASE_A);
+    if (v == 0) dispatch_M<R, FUSE, FLUX, 0>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else if (v == 1) dispatch_M<R, FUSE, FLUX, 1>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else if (v == 2) dispatch_M<R, FUSE, FLUX, 2>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
+    else dispatch_M<R, FUSE, FLUX, 3>(part, g, kc, dk, dt, c, kdx, Nin, Fin, io, tab, nf, nth, q, K, st, s);
 }
 
 template <typename R>

@@ -58,7 +58,7 @@ class RTContext:
 
     def __init__(self, n, dx, bc, M, c_r, sigN, sigE, ebar, flux=0, isothermal=False, X=0.76, Y=0.24,
                  gamma=5.0 / 3.0, a_exp=1.0, x_min=1e-6, N_floor=0.0, max_attempts=100000, fp32=False,
-                 device="cuda", counters=False, smooth=False):
+                 device="cuda", counters=False, smooth=False, otsa=True, brec=(-1, -1, -1)):
         L = lib()
         g = capi.RtGrid()
         g.nx, g.ny, g.nz = (int(v) for v in n)
@@ -73,9 +73,10 @@ class RTContext:
                 gr.sigN[i][j] = float(sigN[i][j])
                 gr.sigE[i][j] = float(sigE[i][j])
             gr.ebar[i] = float(ebar[i])
+            gr.brec[i] = int(brec[i])
         p = capi.RtParams()
         p.flux = int(flux)
-        p.otsa = 1
+        p.otsa = int(bool(otsa))
         p.isothermal = int(bool(isothermal))
         p.prec = capi.RT_PREC_FP32_TRANSPORT if fp32 else capi.RT_PREC_FP64
         p.X, p.Y = float(X), float(Y)
@@ -95,6 +96,7 @@ class RTContext:
         self.c_r = float(c_r)
         self.fp32 = bool(fp32)
         self.smooth = bool(smooth)
+        self.otsa = bool(otsa)
         self.device = torch.device(device)
         nx, ny, nz = self.n
         rdt = torch.float32 if fp32 else torch.float64
@@ -119,7 +121,8 @@ class RTContext:
     def for_workload(cls, w, fp32=False, **over):
         sN, sE, eb, fr = spectrum_attributes(w.spectrum)
         kw = dict(n=w.n, dx=w.dx, bc=w.bc, M=w.spectrum.M, c_r=w.c_r, sigN=sN, sigE=sE, ebar=eb, flux=w.flux,
-                  isothermal=w.isothermal, X=w.X, Y=w.Y, gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min, fp32=fp32)
+                  isothermal=w.isothermal, X=w.X, Y=w.Y, gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min, fp32=fp32,
+                  otsa=w.otsa, brec=w.brec)
         kw.update(over)
         ctx = cls(**kw)
         ctx.group_frac = fr[: w.spectrum.M].copy()

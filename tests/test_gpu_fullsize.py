@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size: 256^3 x 3 groups in the launch
 configuration bench.py times (rt_step: injection, fused transport + first
-chemistry pass, compacted tail), plain and smoothed.  After some steps on the GPU the pre-step
+chemistry pass, compacted tail), plain, smoothed and without OTSA.  After some steps on the GPU the pre-step
 state is copied to the host, the oracle steps sampled cells one by one from
 it (or_step_cells), and the GPU's next rt_step is compared on those cells."""
 import numpy as np
@@ -21,12 +21,15 @@ def host_state(ctx):
             "xHeIII": ctx.xHeIII.cpu().numpy(), "T": ctx.T.cpu().numpy(), "nH": ctx.nH.cpu().numpy()}
 
 
-# smoothed RT (Sec. 4.4) runs with a photon floor of 1e-12 cm^-3
-@pytest.mark.parametrize("fp32,smooth", [(False, False), (True, False), (True, True)])
-def test_256_cubed_sampled_cells_match_oracle(fp32, smooth):
+# smoothed RT (Sec. 4.4) runs with a photon floor of 1e-12 cm^-3; otsa =
+# False: case A with recombination photons (Sec. 3.3.2)
+@pytest.mark.parametrize("fp32,smooth,otsa", [(False, False, True), (True, False, True), (True, True, True),
+                                              (True, False, False)])
+def test_256_cubed_sampled_cells_match_oracle(fp32, smooth, otsa):
     assert torch.cuda.is_available()
     from paper_1304_7126_amd import RTContext
     w = ri.lognormal_256(steps=12)
+    w.otsa = otsa
     floor = 1e-12 if smooth else 0.0
     ctx = RTContext.for_workload(w, fp32=fp32, counters=True, smooth=smooth, N_floor=floor)
     ctx.load_state(ri.initial_state(w))

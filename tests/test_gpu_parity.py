@@ -46,19 +46,21 @@ def gas(n, rng, nH_mean=1e-3):
 
 
 def make_pair(n, bc, M, flux, fp32=False, isothermal=False, X=0.76, Y=0.24, spectrum=None, counters=True,
-              N_floor=0.0, smooth=False):
+              N_floor=0.0, smooth=False, otsa=True):
     RTContext = gpu()
     spec = spectrum or ri.Spectrum(kind="bb", T_bb=1e5, edges_eV={1: ri.EDGES_1, 2: ri.EDGES_2, 3: ri.EDGES_3}[M])
     from paper_1304_7126_amd.runtime import spectrum_attributes
     sN, sE, eb, fr = spectrum_attributes(spec)
     dx = 6.6 * ri.KPC / 128
+    brec = ri.recombination_groups(spec)
     ctx = RTContext(n=n, dx=dx, bc=bc, M=M, c_r=C_R, sigN=sN, sigE=sE, ebar=eb, flux=flux, fp32=fp32,
-                    isothermal=isothermal, X=X, Y=Y, counters=counters, N_floor=N_floor, smooth=smooth)
+                    isothermal=isothermal, X=X, Y=Y, counters=counters, N_floor=N_floor, smooth=smooth,
+                    otsa=otsa, brec=brec)
     ctx.group_frac = fr[:M]
     from oracle import physics
     osN, osE, oeb, ofr = physics.spectrum_attributes(spec)
     o = oracle.OracleRT(n=n, dx=dx, bc=bc, M=M, c_r=C_R, sigN=osN, sigE=osE, ebar=oeb, flux=flux,
-                        isothermal=isothermal, X=X, Y=Y, N_floor=N_floor)
+                        isothermal=isothermal, X=X, Y=Y, N_floor=N_floor, otsa=otsa, brec=brec)
     o.group_frac = ofr[:M]
     return ctx, o
 

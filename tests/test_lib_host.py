@@ -71,8 +71,10 @@ def _init(**over):
 @pytest.mark.parametrize("over,code", [
     (dict(nx=0), capi.RT_EINVAL), (dict(dx=-1.0), capi.RT_EINVAL), (dict(M=4), capi.RT_EINVAL),
     (dict(M=0), capi.RT_EINVAL), (dict(c_r=0.0), capi.RT_EINVAL), (dict(flux=2), capi.RT_EINVAL),
-    (dict(otsa=0), capi.RT_EUNSUPPORTED), (dict(prec=3), capi.RT_EINVAL), (dict(X=0.0), capi.RT_EINVAL),
+    (dict(otsa=2), capi.RT_EINVAL), (dict(prec=3), capi.RT_EINVAL), (dict(X=0.0), capi.RT_EINVAL),
     (dict(gamma=1.0), capi.RT_EINVAL), (dict(x_min=0.0), capi.RT_EINVAL), (dict(max_attempts=0), capi.RT_EINVAL),
+    (dict(smooth=2), capi.RT_EINVAL), (dict(otsa=0, brec=(ctypes.c_int * 3)(0, 1, 0)), capi.RT_EINVAL),
+    (dict(otsa=0, brec=(ctypes.c_int * 3)(-2, 0, 0)), capi.RT_EINVAL),
 ])
 def test_init_rejects_invalid_arguments(over, code):
     rc, h, msg = _init(**over)
