@@ -61,7 +61,10 @@ def parse():
     ap.add_argument("--n-floor", type=float, default=None,
                     help="photon density floor of the 10%% check (default 0; 1e-12 with --smooth)")
     ap.add_argument("--smooth-steps", type=int, default=30,
-                    help="timed steps of the smoothed-vs-plain comparison at floor 1e-12 (0: skip it)")
+                    help="timed steps of the smoothed-vs-plain comparison at floor 1e-12 and of the "
+                         "with/without OTSA comparison (0: skip both)")
+    ap.add_argument("--no-otsa", action="store_true",
+                    help="time the step without the on-the-spot approximation (Sec. 3.3.2) instead")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device 3 times "
                          "(reference kernel for HBM byte counters)")
@@ -106,7 +109,7 @@ def cpu_baseline(seconds, n_full, M):
                       f"from the initial state, {el:.1f} s wall"}
 
 
-def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, floor=0.0, nH_mean=1e-3):
+def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, floor=0.0, nH_mean=1e-3, otsa=True):
     """The lognormal n^3 x 3 workload: build it, run `warmup` steps, then time
     `steps` rt_step calls (injection, transport fused with the first
     chemistry pass, the compacted tail), with the library's HIP events
@@ -118,9 +121,10 @@ def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, flo
     flux = ri.FLUX_HLL if flux_name == "hll" else ri.FLUX_GLF
     w = ri.lognormal_box(n, 13.2 * n / 256, max(1, round(200 * (n / 256) ** 3)), steps=steps, seed=0, flux=flux)
     w.nH_mean = nH_mean
+    w.otsa = otsa
     M = w.spectrum.M
-    print(f"# building {n}^3 x {M} workload (mean n_H {nH_mean:g}, smooth={smooth}, N_floor={floor:g})",
-          file=sys.stderr, flush=True)
+    print(f"# building {n}^3 x {M} workload (mean n_H {nH_mean:g}, smooth={smooth}, N_floor={floor:g}, "
+          f"otsa={otsa})", file=sys.stderr, flush=True)
     st = ri.initial_state(w)
     ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
     ctx = RTContext.for_workload(w, fp32=fp32, smooth=smooth, N_floor=floor)
@@ -173,6 +177,24 @@ def smoothing_comparison(n, fp32, flux_name, steps, warmup, head_attempts):
                                                   d["smoothed"]["substeps_per_cell_step"])
         d["time_ratio_plain_over_smoothed"] = d["plain"]["ms_per_step"] / d["smoothed"]["ms_per_step"]
         out[name] = d
+    return out
+
+
+def otsa_comparison(n, fp32, flux_name, steps, warmup, head_attempts):
+    """The headline workload with and without the on-the-spot approximation
+    (Sec. 3.3.2: case A rates and recombination photons into the group
+    holding each species' threshold), same steps timed."""
+    out = {"timed_steps": steps, "warmup": warmup}
+    for otsa in (True, False):
+        r = grid_run(n, fp32, flux_name, steps, warmup, head_attempts, otsa=otsa)
+        s = r["stats"]
+        nc = r["w"].ncell
+        out["otsa" if otsa else "case_A_with_emission"] = {
+            "value": r["cgu"], "unit": "cell-group updates/s", "ms_per_step": r["ms"],
+            "substeps_per_cell_step": s["substeps_total"] / (nc * steps),
+            "attempts_max": s["attempts_max"], "flags": s["flags"],
+            "ms_per_launch": {k: r["per"][k] for k in ("inject", "head", "tail")}}
+    out["time_ratio"] = out["case_A_with_emission"]["ms_per_step"] / out["otsa"]["ms_per_step"]
     return out
 
 
@@ -305,7 +327,8 @@ def main():
     fp32 = not args.fp64
     n = args.n
     floor = args.n_floor if args.n_floor is not None else (1e-12 if args.smooth else 0.0)
-    r = grid_run(n, fp32, args.flux, args.steps, args.warmup, args.head_attempts, args.smooth, floor)
+    r = grid_run(n, fp32, args.flux, args.steps, args.warmup, args.head_attempts, args.smooth, floor,
+                 otsa=not args.no_otsa)
     w, M, K, s, ms, cgu, per = r["w"], r["M"], args.steps, r["stats"], r["ms"], r["cgu"], r["per"]
 
     rad, gas = algorithmic_bytes(M, fp32)
@@ -316,7 +339,7 @@ def main():
     t_head = per["head"]
     achieved = step_bytes / (t_head * 1e-3) / 1e9
     counters_valid = (kernel_source_hash() == COUNTERS_SOURCE_HASH and fp32 and n == 256 and args.flux == "hll"
-                      and not args.smooth and floor == 0.0)
+                      and not args.smooth and floor == 0.0 and not args.no_otsa)
     traffic = COUNTERS["read_bytes"] + COUNTERS["write_bytes"] if counters_valid else None
     # the kernel is bound by its VALU issue rate: counter figures (static,
     # from the profile) and the live duration
@@ -337,6 +360,8 @@ def main():
     wl = f"lognormal {n}^3 x {M} groups, 200 sources, {args.flux.upper()}, c_r=c/100"
     if args.smooth or floor > 0:
         wl += f"{', smoothed RT' if args.smooth else ''}, N_floor={floor:g}"
+    if args.no_otsa:
+        wl += ", no OTSA (case A, recombination photons)"
     out = {
         "metric": "RT cell-group updates/s at 256^3 x 3 groups; adjoint/forward cost ratio",
         "value": cgu,
@@ -352,16 +377,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl,
                    "grid": [n, n, n], "groups": M, "flux": args.flux, "precision": "mixed" if fp32 else "fp64",
-                   "smooth": bool(args.smooth), "N_floor": floor, "parallelism": "1 GPU"},
+                   "smooth": bool(args.smooth), "otsa": not args.no_otsa, "N_floor": floor,
+                   "parallelism": "1 GPU"},
         "chem": {"substeps_per_cell_step": s["substeps_total"] / (w.ncell * K),
                  "attempts_per_cell_step": s["attempts_total"] / (w.ncell * K),
                  "attempts_max": s["attempts_max"], "flags": s["flags"]},
         "roofline": roof,
     }
     torch.cuda.empty_cache()
-    if args.smooth_steps > 0 and not args.smooth:
+    if args.smooth_steps > 0 and not args.smooth and not args.no_otsa:
         out["smoothing"] = smoothing_comparison(n, fp32, args.flux, args.smooth_steps, args.warmup,
                                                 args.head_attempts)
+        torch.cuda.empty_cache()
+        out["recombination_photons"] = otsa_comparison(n, fp32, args.flux, args.smooth_steps, args.warmup,
+                                                       args.head_attempts)
         torch.cuda.empty_cache()
     if not args.no_adjoint:
         print("# adjoint cost (64^3 differentiation workload)", file=sys.stderr, flush=True)
