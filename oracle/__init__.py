@@ -89,6 +89,7 @@ class OrParams(ctypes.Structure):
         ("hll", ctypes.POINTER(ctypes.c_double)),
         ("hll_nf", ctypes.c_int), ("hll_nth", ctypes.c_int),
         ("brec", ctypes.c_int * 3),
+        ("inflow", (ctypes.c_double * 3) * 6),
     ]
 
 
@@ -136,7 +137,7 @@ class OracleRT:
 
     def __init__(self, n, dx, bc, M, c_r, sigN, sigE, ebar, flux=0, otsa=True,
                  isothermal=False, X=0.76, Y=0.24, gamma=5.0 / 3.0, a_exp=1.0, x_min=1e-6,
-                 N_floor=0.0, max_attempts=100000, hll=None, brec=(-1, -1, -1)):
+                 N_floor=0.0, max_attempts=100000, hll=None, brec=(-1, -1, -1), inflow=None):
         p = OrParams()
         p.nx, p.ny, p.nz = (int(v) for v in n)
         p.dx = float(dx)
@@ -160,6 +161,11 @@ class OracleRT:
         p.max_attempts = int(max_attempts)
         for j in range(3):
             p.brec[j] = int(brec[j])
+        if inflow is not None:
+            inflow = np.asarray(inflow, np.float64).reshape(6, -1)
+            for f in range(6):
+                for g in range(min(3, inflow.shape[1])):
+                    p.inflow[f][g] = float(inflow[f, g])
         self._hll = np.ascontiguousarray(hll if hll is not None else hll_table(), dtype=np.float64)
         p.hll = _dp(self._hll)
         p.hll_nf, p.hll_nth = self._hll.shape[0], self._hll.shape[1]
@@ -174,7 +180,8 @@ class OracleRT:
         sigN, sigE, ebar, frac = physics.spectrum_attributes(w.spectrum)
         kw = dict(n=w.n, dx=w.dx, bc=w.bc, M=w.spectrum.M, c_r=w.c_r, sigN=sigN, sigE=sigE,
                   ebar=ebar, flux=w.flux, otsa=w.otsa, isothermal=w.isothermal, X=w.X, Y=w.Y,
-                  gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min, brec=w.brec)
+                  gamma=w.gamma, a_exp=w.a_exp, x_min=w.x_min, brec=w.brec,
+                  inflow=w.inflow_flux(frac))
         kw.update(over)
         o = cls(**kw)
         o.group_frac = frac[: w.spectrum.M].copy()

@@ -42,7 +42,7 @@
 #define OR_FLAG_NAN   2u   /* non-finite value in the result             */
 #define OR_FLAG_NNEG  8u   /* negative photon density after the update   */
 
-enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_REFLECT = 2 };
+enum { OR_BC_PERIODIC = 0, OR_BC_OUTFLOW = 1, OR_BC_REFLECT = 2, OR_BC_INFLOW = 3 };
 enum { OR_FLUX_GLF = 0, OR_FLUX_HLL = 1 };
 
 typedef struct {
@@ -68,6 +68,8 @@ typedef struct {
     int brec[3];               /* without OTSA: the group receiving the recombination
                                 * photons of HII, HeII, HeIII (b^rec of eq. cool_N_cr),
                                 * -1: none */
+    double inflow[6][3];       /* OR_BC_INFLOW faces: photon flux [s^-1 cm^-2] per group
+                                * entering the box through the face (the Iliev test 3 source) */
 } or_params;
 
 /* ======================================================================
@@ -395,7 +397,17 @@ static void neighbour_U(const or_params *p, const double *N, const double *F, in
     size_t nc = (size_t)p->nx * p->ny * p->nz;
     int reflect = 0;
     if (j < 0 || j >= n[d]) {
-        int bc = p->bc[2 * d + (s > 0 ? 1 : 0)];
+        int face = 2 * d + (s > 0 ? 1 : 0);
+        int bc = p->bc[face];
+        if (bc == OR_BC_INFLOW) {
+            /* the ghost cell holds a beam entering the box: N = F / c_r
+             * (reduced flux 1) with F along the inward normal */
+            double f = p->inflow[face][g];
+            U[0] = f / p->c_r;
+            U[1] = U[2] = U[3] = 0.0;
+            U[1 + d] = s < 0 ? f : -f;
+            return;
+        }
         if (bc == OR_BC_PERIODIC) {
             j = (j + n[d]) % n[d];
         } else {
@@ -407,6 +419,26 @@ static void neighbour_U(const or_params *p, const double *N, const double *F, in
     size_t i = (size_t)c[0] + (size_t)p->nx * ((size_t)c[1] + (size_t)p->ny * c[2]);
     load_U(N, F, nc, g, i, U);
     if (reflect) U[1 + d] = -U[1 + d];
+}
+
+/* After an HLL update a flux above c_r N (reduced flux f > 1, reachable by
+ * rounding next to an exact beam) is scaled back to c_r N.  The paper does
+ * not say how unrealisable states are treated; left alone, an exact beam
+ * entering through a face grows an instability under HLL, whose wave speeds
+ * at f = 1 are both +c while the closure capped at f = 1 propagates a
+ * backward wave.  N <= 0 is left as it is. */
+static void limit_flux(double U[4], double c)
+{
+    if (!(U[0] > 0.0)) return;
+    double a[3], a2 = 0.0;
+    for (int d = 0; d < 3; d++) {
+        a[d] = U[1 + d] / (c * U[0]);
+        a2 += a[d] * a[d];
+    }
+    if (a2 > 1.0) {
+        double s = 1.0 / sqrt(a2);
+        for (int d = 0; d < 3; d++) U[1 + d] *= s;
+    }
 }
 
 /* U' = U + dt/dx * sum_d (Phi_{d,l-1/2} - Phi_{d,l+1/2})   (eq. dUdt_sol),
@@ -433,9 +465,11 @@ void or_transport(const or_params *p, double dt, const double *N, const double *
                 or_face_flux(p, d, UC, UR, Pp);
                 for (int m = 0; m < 4; m++) acc[m] += Pm[m] - Pp[m];
             }
-            Nout[(size_t)g * nc + i] = UC[0] + k * acc[0];
-            for (int d = 0; d < 3; d++)
-                Fout[(size_t)(3 * g + d) * nc + i] = UC[1 + d] + k * acc[1 + d];
+            double Un[4];
+            for (int m = 0; m < 4; m++) Un[m] = UC[m] + k * acc[m];
+            if (p->flux == OR_FLUX_HLL) limit_flux(Un, p->c_r);
+            Nout[(size_t)g * nc + i] = Un[0];
+            for (int d = 0; d < 3; d++) Fout[(size_t)(3 * g + d) * nc + i] = Un[1 + d];
         }
     }
 }
@@ -826,8 +860,11 @@ unsigned or_step_cells_smooth(const or_params *p, double dt, const double *N, co
                 or_face_flux(p, d, UC, UR, Pp);
                 for (int m = 0; m < 4; m++) acc[m] += Pm[m] - Pp[m];
             }
-            Nc[g] = UC[0] + k * acc[0];
-            for (int d = 0; d < 3; d++) Fc[3 * g + d] = UC[1 + d] + k * acc[1 + d];
+            double Un[4];
+            for (int m = 0; m < 4; m++) Un[m] = UC[m] + k * acc[m];
+            if (p->flux == OR_FLUX_HLL) limit_flux(Un, p->c_r);
+            Nc[g] = Un[0];
+            for (int d = 0; d < 3; d++) Fc[3 * g + d] = Un[1 + d];
         }
         x3[0] = xHII[i];
         x3[1] = xHeII[i];

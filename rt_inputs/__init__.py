@@ -32,7 +32,7 @@ EDGES_3 = (13.6, 24.59, 54.42, np.inf)
 EDGES_2 = (13.6, 24.59, np.inf)
 EDGES_1 = (13.6, np.inf)
 
-BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_INFLOW = 0, 1, 2, 3
 FLUX_GLF, FLUX_HLL = 0, 1
 
 
@@ -107,10 +107,27 @@ class Workload:
     sigma_ln: float = 0.0          # 0 -> uniform density
     n_sources: int = 1
     seed: int = 0
+    # a uniform sphere of other gas: ((centre x, y, z) [cm], radius [cm], n_H, T, x_HII)
+    clump: Optional[tuple] = None
+    # photons s^-1 cm^-2 entering through each BC_INFLOW face, summed over groups
+    inflow_total: Optional[Sequence[float]] = None
 
     @property
     def dx(self) -> float:
         return self.L / self.n[0]
+
+    def inflow_flux(self, group_frac) -> np.ndarray:
+        """(6, M) photon flux per face and group entering through the
+        BC_INFLOW faces: the total split by the groups' photon fractions."""
+        M = self.spectrum.M
+        out = np.zeros((6, M))
+        if self.inflow_total is not None:
+            f = np.asarray(group_frac[:M], np.float64)
+            f = f / f.sum()
+            for face in range(6):
+                if self.bc[face] == BC_INFLOW:
+                    out[face] = self.inflow_total[face] * f
+        return out
 
     @property
     def brec(self) -> tuple:
@@ -176,7 +193,7 @@ def initial_state(w: Workload):
     else:
         nH = np.full(shp, w.nH_mean)
     M = w.spectrum.M
-    return {
+    st = {
         "nH": nH,
         "xHII": np.full(shp, w.xHII0),
         "xHeII": np.full(shp, w.xHeII0),
@@ -185,6 +202,16 @@ def initial_state(w: Workload):
         "N": np.zeros((M,) + shp),
         "F": np.zeros((M, 3) + shp),
     }
+    if w.clump is not None:
+        (xc, yc, zc), r, n_in, T_in, x_in = w.clump
+        dx = w.dx
+        z, y, x = np.meshgrid((np.arange(nz) + 0.5) * dx, (np.arange(ny) + 0.5) * dx, (np.arange(nx) + 0.5) * dx,
+                              indexing="ij")
+        inside = (x - xc) ** 2 + (y - yc) ** 2 + (z - zc) ** 2 <= r * r
+        st["nH"][inside] = n_in
+        st["T"][inside] = T_in
+        st["xHII"][inside] = x_in
+    return st
 
 
 # ---- the paper-derived workloads -----------------------------------------
@@ -200,6 +227,24 @@ def stromgren_32(steps: int = 100) -> Workload:
                     bc=(BC_REFLECT, BC_OUTFLOW) * 3, spectrum=MONO_13p6,
                     X=1.0, Y=0.0, T0=1e4, xHII0=1.2e-3, xHeII0=0.0, xHeIII0=0.0,
                     isothermal=True, flux=FLUX_GLF, steps=steps)
+
+
+def shadow_clump(n: int = 128, steps: int = 100) -> Workload:
+    """Iliev test 3 (Sec. 6) on a uniform n^3 grid: a 6.6 kpc box of hydrogen
+    (n_H = 2e-4, T = 8000 K, x_HII at the floor 1e-6) with a sphere of radius
+    0.8 kpc at (5, 3.3, 3.3) kpc of 200x denser gas (T = 40 K, x_HII = 1e-6);
+    a constant flux of 1e6 photons s^-1 cm^-2 enters through the x = 0 face,
+    the other faces let radiation out; three groups of a 1e5 K blackbody,
+    HLL, OTSA, c_r = c/10, T evolving.  No point sources."""
+    L = 6.6 * KPC
+    return Workload(name=f"shadow_clump_{n}", n=(n, n, n), L=L,
+                    bc=(BC_INFLOW, BC_OUTFLOW, BC_OUTFLOW, BC_OUTFLOW, BC_OUTFLOW, BC_OUTFLOW),
+                    spectrum=Spectrum(kind="bb", T_bb=1e5, edges_eV=EDGES_3),
+                    X=1.0, Y=0.0, T0=8000.0, xHII0=1e-6, xHeII0=0.0, xHeIII0=0.0,
+                    isothermal=False, flux=FLUX_HLL, steps=steps, c_r=C_LIGHT / 10.0,
+                    nH_mean=2e-4, n_sources=0,
+                    clump=((5.0 * KPC, 3.3 * KPC, 3.3 * KPC), 0.8 * KPC, 4e-2, 40.0, 1e-6),
+                    inflow_total=(1e6, 0, 0, 0, 0, 0))
 
 
 def lognormal_box(n: int, L_kpc: float, n_sources: int, steps: int, seed: int = 0,
