@@ -48,7 +48,7 @@ typedef enum {
     RT_EUNSUPPORTED = -5  /* option not supported                        */
 } rt_status;
 
-enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW = 1, RT_BC_REFLECT = 2 };
+enum { RT_BC_PERIODIC = 0, RT_BC_OUTFLOW = 1, RT_BC_REFLECT = 2, RT_BC_INFLOW = 3 };
 enum { RT_FLUX_GLF = 0, RT_FLUX_HLL = 1 };
 /* RT_PREC_FP64: N, F stored and transported in FP64.
  * RT_PREC_FP32_TRANSPORT: N, F stored and transported in FP32; the
@@ -64,8 +64,10 @@ enum { RT_PREC_FP64 = 0, RT_PREC_FP32_TRANSPORT = 1 };
 
 /* Grid: nx, ny, nz >= 1 cells of width dx [cm].  bc[] for the faces
  * -x,+x,-y,+y,-z,+z: periodic (must be set on both faces of an axis),
- * outflow (ghost cell copies the boundary cell) or reflect (ghost mirrors
- * the boundary cell with the normal flux component negated). */
+ * outflow (ghost cell copies the boundary cell), reflect (ghost mirrors
+ * the boundary cell with the normal flux component negated) or inflow
+ * (ghost holds a beam entering the grid, set by rt_set_inflow; zero until
+ * then). */
 typedef struct {
     int nx, ny, nz;
     double dx;
@@ -199,6 +201,13 @@ rt_status rt_set_current(rt_ctx *ctx, int set);
  * Sources in one cell are summed in input order.  n = 0 removes all. */
 rt_status rt_set_sources(rt_ctx *ctx, int n, const int32_t *ijk, const double *ndot);
 
+/* Boundary-flux source (the x = 0 face of Iliev test 3, Sec. 6): face (0..5,
+ * -x,+x,-y,+y,-z,+z) must be an RT_BC_INFLOW face; host flux[g] >= 0 is the
+ * photon flux [s^-1 cm^-2] of group g entering through it, held by the
+ * ghost cell as a beam N = flux / c_r along the inward normal.  Returns
+ * RT_EINVAL for another face kind or a negative or non-finite flux. */
+rt_status rt_set_inflow(rt_ctx *ctx, int face, const double *flux);
+
 /* Courant-limited step dt = courant * dx / (3 c_r) (Sec. 4.1, eq.
  * dt_courant, with the factor 0.8 of the paper's tests). */
 rt_status rt_courant_dt(const rt_ctx *ctx, double courant, double *dt);
@@ -212,7 +221,9 @@ rt_status rt_courant_dt(const rt_ctx *ctx, double courant, double *dt);
 rt_status rt_inject(rt_ctx *ctx, double dt);
 
 /* Transport (Sec. 3.2) of every group over dt from the current set into the
- * other set, which then becomes current.  dt must satisfy dt <= dx/(3 c_r). */
+ * other set, which then becomes current.  dt must satisfy dt <= dx/(3 c_r).
+ * With HLL a flux that comes out above c_r N (N > 0) is scaled back to
+ * c_r N; without it an exact beam next to an inflow face is unstable. */
 rt_status rt_transport(rt_ctx *ctx, double dt);
 
 /* Thermochemistry (App. A) of every cell over dt on the current set.  With

@@ -429,10 +429,12 @@ static void neighbour_U(const or_params *p, const double *N, const double *F, in
  * backward wave.  N <= 0 is left as it is. */
 static void limit_flux(double U[4], double c)
 {
-    if (!(U[0] > 0.0)) return;
+    /* as in the closure, a density so small that 1/(c_r N) overflows counts as empty */
+    double icn = 1.0 / (c * U[0]);
+    if (!(U[0] > 0.0) || isinf(icn)) return;
     double a[3], a2 = 0.0;
     for (int d = 0; d < 3; d++) {
-        a[d] = U[1 + d] / (c * U[0]);
+        a[d] = U[1 + d] * icn;
         a2 += a[d] * a[d];
     }
     if (a2 > 1.0) {

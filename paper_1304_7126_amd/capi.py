@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librtm1.so")
 
 RT_OK, RT_EINVAL, RT_EHIP, RT_ENOMEM, RT_ESTATE, RT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-RT_BC_PERIODIC, RT_BC_OUTFLOW, RT_BC_REFLECT = 0, 1, 2
+RT_BC_PERIODIC, RT_BC_OUTFLOW, RT_BC_REFLECT, RT_BC_INFLOW = 0, 1, 2, 3
 RT_FLUX_GLF, RT_FLUX_HLL = 0, 1
 RT_PREC_FP64, RT_PREC_FP32_TRANSPORT = 0, 1
 RT_FLAG_CAP, RT_FLAG_NAN, RT_FLAG_NNEG, RT_FLAG_TRACE = 1, 2, 8, 16
@@ -26,6 +26,7 @@ EXPORTED = [
     "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
     "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint", "rt_set_accounting",
+    "rt_set_inflow",
 ]
 
 
@@ -130,6 +131,8 @@ def lib():
     L.rt_reset_stats.restype = st
     L.rt_set_accounting.argtypes = [vp, ctypes.c_int]
     L.rt_set_accounting.restype = st
+    L.rt_set_inflow.argtypes = [vp, ctypes.c_int, dp]
+    L.rt_set_inflow.restype = st
     L.rt_group_attributes.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp]
     L.rt_group_attributes.restype = st
     L.rt_hll_table.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int),

@@ -322,7 +322,7 @@ static rt_status validate(const rt_grid *g, const rt_groups *gr, const rt_params
     if ((double)g->nx * g->ny * g->nz > 2.0e9) { err = "grid too large (> 2e9 cells)"; return RT_EINVAL; }
     if (!(g->dx > 0) || !std::isfinite(g->dx)) { err = "dx must be positive"; return RT_EINVAL; }
     for (int f = 0; f < 6; ++f)
-        if (g->bc[f] < 0 || g->bc[f] > 2) { snprintf(b, sizeof b, "bc[%d] invalid", f); err = b; return RT_EINVAL; }
+        if (g->bc[f] < 0 || g->bc[f] > 3) { snprintf(b, sizeof b, "bc[%d] invalid", f); err = b; return RT_EINVAL; }
     for (int d = 0; d < 3; ++d)
         if ((g->bc[2 * d] == RT_BC_PERIODIC) != (g->bc[2 * d + 1] == RT_BC_PERIODIC)) {
             snprintf(b, sizeof b, "axis %d: periodic must be set on both faces", d);
@@ -373,6 +373,7 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     for (int f = 0; f < 6; ++f) c->grid.bc[f] = grid->bc[f];
     c->grid.ncell = (size_t)grid->nx * grid->ny * grid->nz;
     c->grid.dx = grid->dx;
+    memset(c->grid.inflow, 0, sizeof c->grid.inflow);
     c->groups = *groups;
     c->params = *params;
     c->fp32 = params->prec == RT_PREC_FP32_TRANSPORT;
@@ -556,6 +557,18 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
         RT_HIP(c, hipMalloc((void **)&c->src_prev, rates.size() * sizeof(double)));
         RT_HIP(c, launch_source_map(c->src_map, c->grid.ncell, c->src_cell, c->nsrc, c->stream));
     }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_inflow(rt_ctx *c, int face, const double *flux)
+{
+    if (!c) return RT_EINVAL;
+    if (face < 0 || face > 5) RT_FAIL(c, RT_EINVAL, "face must be 0..5");
+    if (c->grid.bc[face] != RT_BC_INFLOW) RT_FAIL(c, RT_EINVAL, "face %d is not an RT_BC_INFLOW face", face);
+    if (!flux) RT_FAIL(c, RT_EINVAL, "null flux");
+    for (int g = 0; g < c->groups.M; ++g)
+        if (!(flux[g] >= 0) || !std::isfinite(flux[g])) RT_FAIL(c, RT_EINVAL, "flux must be finite and >= 0");
+    for (int g = 0; g < 3; ++g) c->grid.inflow[face][g] = g < c->groups.M ? flux[g] : 0.0;
     return RT_OK;
 }
 

@@ -191,7 +191,7 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
         for (int grp = 0; grp < M; ++grp) {
             double bout = 0.0;  // boundary outflow (not accounted in batches)
             const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc, Fin + (size_t)3 * grp * nc, c,
-                                                    (R)b.kdx, tab, nf, nth, bout);
+                                                    (R)b.kdx, tab, nf, nth, bout, b.g, grp);
             s.N[grp] = (double)o.n;
             Fout[(size_t)(3 * grp) * nc + i] = o.fx;
             Fout[(size_t)(3 * grp + 1) * nc + i] = o.fy;

@@ -35,11 +35,13 @@ __device__ __forceinline__ R comp(const U4<R> &u, int d)
 
 // The six neighbours of a cell (-x,+x,-y,+y,-z,+z) with the ghost cells
 // of the boundary conditions: periodic wraps, outflow repeats the cell,
-// reflect repeats it with the normal flux component negated (bit d of refl).
+// reflect repeats it with the normal flux component negated (bit d of refl),
+// inflow holds a beam entering the grid.
 struct Nbr {
     uint32_t idx[6];
-    unsigned refl;   // bit f: face f's ghost mirrors the normal flux
-    unsigned ghost;  // bit f: face f is a boundary face (outflow or reflect)
+    unsigned refl;    // bit f: face f's ghost mirrors the normal flux
+    unsigned ghost;   // bit f: face f is a boundary face (outflow, reflect or inflow)
+    unsigned inflow;  // bit f: face f's ghost is the entering beam
 };
 
 __device__ __forceinline__ void cell_coords(const KGrid &g, uint32_t i, int &ix, int &iy, int &iz)
@@ -56,6 +58,7 @@ __device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, in
     Nbr nb;
     nb.refl = 0;
     nb.ghost = 0;
+    nb.inflow = 0;
     const int c[3] = {ix, iy, iz};
     const int n[3] = {g.nx, g.ny, g.nz};
     const uint32_t stride[3] = {1u, (uint32_t)g.nx, (uint32_t)g.nx * (uint32_t)g.ny};
@@ -70,6 +73,7 @@ __device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, in
             nb.idx[2 * d] = i;
             nb.ghost |= 1u << (2 * d);
             if (g.bc[2 * d] == 2) nb.refl |= 1u << (2 * d);
+            if (g.bc[2 * d] == 3) nb.inflow |= 1u << (2 * d);
         }
         // high side
         if (c[d] < n[d] - 1) {
@@ -80,6 +84,7 @@ __device__ __forceinline__ Nbr neighbours(const KGrid &g, uint32_t i, int ix, in
             nb.idx[2 * d + 1] = i;
             nb.ghost |= 1u << (2 * d + 1);
             if (g.bc[2 * d + 1] == 2) nb.refl |= 1u << (2 * d + 1);
+            if (g.bc[2 * d + 1] == 3) nb.inflow |= 1u << (2 * d + 1);
         }
     }
     return nb;
@@ -128,7 +133,21 @@ __device__ __forceinline__ void face_flux(const U4<R> &L, const R PL[6], R lLm, 
     for (int m = 0; m < 4; ++m) Phi[m] = (lp * GL[m] - lm * GR[m] + lp * lm * (uR[m] - uL[m])) * iden;
 }
 
-// Transport of one group of one cell: every face flux from the source
+// The ghost state of an inflow face: a beam of photon flux f along the
+// inward normal (sgn = +1 on a low face, -1 on a high face), N = f / c.
+template <typename R>
+__device__ __forceinline__ U4<R> beam(double f, int d, double sgn, R c)
+{
+    U4<R> u;
+    u.n = (R)(f / (double)c);
+    const R fd = (R)(sgn * f);
+    u.fx = d == 0 ? fd : R(0);
+    u.fy = d == 1 ? fd : R(0);
+    u.fz = d == 2 ? fd : R(0);
+    return u;
+}
+
+// Transport of group grp of one cell: every face flux from the source
 // arrays (N, F of this group),
 //   U' = U + dt/dx * sum_d (Phi_{d,-1/2} - Phi_{d,+1/2})     (eq. dUdt_sol)
 // bout receives the photon-density flux out of the grid through the cell's
@@ -136,7 +155,7 @@ __device__ __forceinline__ void face_flux(const U4<R> &L, const R PL[6], R lLm, 
 template <typename R, int FLUX>
 __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_t nc, const R *__restrict__ N,
                                                 const R *__restrict__ F, R c, R kdx, const R *__restrict__ tab,
-                                                int nf, int nth, double &bout)
+                                                int nf, int nth, double &bout, const KGrid &g, int grp)
 {
     const U4<R> C = load_u(N, F, nc, i);
     R PC[6];
@@ -156,6 +175,8 @@ __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_
             else if (d == 1) Rt.fy = -Rt.fy;
             else Rt.fz = -Rt.fz;
         }
+        if (nb.inflow & (1u << (2 * d))) L = beam<R>(g.inflow[2 * d][grp], d, 1.0, c);
+        if (nb.inflow & (1u << (2 * d + 1))) Rt = beam<R>(g.inflow[2 * d + 1][grp], d, -1.0, c);
         R PL[6], PR[6], Pm[4], Pp[4];
         m1_pressure(L.n, L.fx, L.fy, L.fz, c, PL);
         m1_pressure(Rt.n, Rt.fx, Rt.fy, Rt.fz, c, PR);
@@ -177,6 +198,7 @@ __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_
     o.fx = C.fx + kdx * acc[1];
     o.fy = C.fy + kdx * acc[2];
     o.fz = C.fz + kdx * acc[3];
+    if (FLUX == 1) limit_flux(o.n, o.fx, o.fy, o.fz, c);
     return o;
 }
 

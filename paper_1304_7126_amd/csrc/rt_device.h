@@ -74,6 +74,25 @@ __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6])
     P[5] = B * ay * az;
 }
 
+// After an HLL update a flux above c N is scaled back to c N: at f > 1 the
+// capped closure propagates a backward wave that the table's speeds (both
+// +c at f = 1) do not resolve, and an exact beam next to its source face
+// would grow it from rounding.  Empty (and vanishing) densities are left.
+template <typename R>
+__device__ __forceinline__ void limit_flux(R N, R &Fx, R &Fy, R &Fz, R c)
+{
+    const R icN = rcp(c * N);
+    if (!(N > R(0)) || isinf(icN)) return;
+    const R ax = Fx * icN, ay = Fy * icN, az = Fz * icN;
+    const R a2 = ax * ax + ay * ay + az * az;
+    if (a2 > R(1)) {
+        const R s = R(1) / sqrt(a2);
+        Fx *= s;
+        Fy *= s;
+        Fz *= s;
+    }
+}
+
 // components (c^2 P_dx, c^2 P_dy, c^2 P_dz) of row d
 template <typename R>
 __device__ __forceinline__ void prow(const R P[6], int d, R &px, R &py, R &pz)

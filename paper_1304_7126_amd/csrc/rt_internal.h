@@ -13,6 +13,7 @@ struct KGrid {
     int bc[6];
     size_t ncell;
     double dx;
+    double inflow[6][3];  // RT_BC_INFLOW faces: photon flux [s^-1 cm^-2] entering, per group
 };
 
 struct KChem {

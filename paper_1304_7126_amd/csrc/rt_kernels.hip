@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_transport(KGrid g, int M, R c, R kdx, c
         for (int grp = 0; grp < M; ++grp) {
             double bout = 0.0;
             const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc, Fin + (size_t)3 * grp * nc,
-                                                    c, kdx, tab, nf, nth, bout);
+                                                    c, kdx, tab, nf, nth, bout, g, grp);
             Nout[(size_t)grp * nc + i] = o.n;
             R *Fo = Fout + (size_t)3 * grp * nc;
             Fo[i] = o.fx;
@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
             for (int grp = 0; grp < M; ++grp) {
                 double bout = 0.0;
                 const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc,
-                                                        Fin + (size_t)3 * grp * nc, c, kdx, tab, nf, nth, bout);
+                                                        Fin + (size_t)3 * grp * nc, c, kdx, tab, nf, nth, bout, g,
+                                                        grp);
                 s.N[grp] = (double)o.n;
                 av[grp] = (double)o.n;
                 av[3 + grp] = bout;

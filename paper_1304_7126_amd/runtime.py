@@ -126,6 +126,10 @@ class RTContext:
         kw.update(over)
         ctx = cls(**kw)
         ctx.group_frac = fr[: w.spectrum.M].copy()
+        inflow = w.inflow_flux(fr)
+        for face in range(6):
+            if w.bc[face] == capi.RT_BC_INFLOW:
+                ctx.set_inflow(face, inflow[face])
         return ctx
 
     def _bind(self):
@@ -220,6 +224,12 @@ class RTContext:
                 "attempts_max": s.attempts_max, "flags": s.flags, "injected": list(s.injected)[:M],
                 "absorbed": list(s.absorbed)[:M], "outflow": list(s.outflow)[:M],
                 "substep_hist": list(s.substep_hist)}
+
+    def set_inflow(self, face, flux):
+        """Photon flux [s^-1 cm^-2] per group entering through an
+        RT_BC_INFLOW face (0..5 = -x,+x,-y,+y,-z,+z)."""
+        f = np.ascontiguousarray(np.asarray(flux, np.float64).reshape(self.M))
+        check(lib().rt_set_inflow(self._h, int(face), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._h)
 
     def set_accounting(self, enabled=True):
         """Photon accounting (injected, absorbed, outflow, substep histogram)."""
