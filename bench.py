@@ -55,8 +55,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--head-attempts", type=int, default=0, help="chemistry attempts per cell in the first pass")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
-    ap.add_argument("--form", choices=["grid", "batch", "adjoint"], default="grid",
-                    help="grid: the 256^3 x 3 headline; batch: 64 uneven boxes, batched vs one-by-one")
+    ap.add_argument("--form", choices=["grid", "batch", "adjoint", "shadow"], default="grid",
+                    help="grid: the 256^3 x 3 headline; batch: 64 uneven boxes, batched vs one-by-one; "
+                         "shadow: Iliev test 3 (dense clump lit from the x = 0 face) at 128^3 to 15 Myr")
+    ap.add_argument("--shadow-myr", type=float, default=15.0, help="simulated time of --form shadow [Myr]")
     ap.add_argument("--smooth", action="store_true", help="time the smoothed RT step (Sec. 4.4) instead")
     ap.add_argument("--n-floor", type=float, default=None,
                     help="photon density floor of the 10%% check (default 0; 1e-12 with --smooth)")
@@ -198,6 +200,79 @@ def otsa_comparison(n, fp32, flux_name, steps, warmup, head_attempts):
     return out
 
 
+def bench_shadow(args):
+    """Iliev test 3 (Sec. 6) on a uniform 128^3 grid: a flux of 1e6 photons
+    s^-1 cm^-2 enters through the x = 0 face, a clump of 200x denser gas
+    traps the I-front and casts a shadow; HLL, three groups, c_r = c/10, run
+    to 15 Myr.  Reports the step rate and the quantities the paper plots:
+    the I-front position on the axis (x_HII = 0.5, relative to the clump
+    centre, in units of the clump's Stromgren length 0.78 kpc) and the mean
+    ionised fraction and temperature inside the clump at 1, 3 and 15 Myr."""
+    import numpy as np
+    import torch
+
+    import rt_inputs as ri
+    from paper_1304_7126_amd import RTContext
+    w = ri.shadow_clump(128)
+    st = ri.initial_state(w)
+    ctx = RTContext.for_workload(w)
+    ctx.load_state(st)
+    inside = st["nH"] > 1e-3
+    del st
+    dt = ctx.courant_dt()
+    myr = 3.15576e13
+    marks = sorted({m for m in (1.0, 3.0, args.shadow_myr) if m <= args.shadow_myr})
+    targets = [int(round(m * myr / dt)) for m in marks]
+    n = w.n[0]
+    dx = w.dx
+    xs = (np.arange(n) + 0.5) * dx
+
+    def snapshot(t_myr):
+        x = ctx.xHII.cpu().numpy()
+        T = ctx.T.cpu().numpy()
+        axis = x[n // 2, n // 2, :]
+        # the I-front: the last x_HII = 0.5 crossing on the axis before the
+        # neutral gas (the clump or the shadow behind it)
+        k = int(np.argmax(axis < 0.5)) if np.any(axis < 0.5) else n - 1
+        if 0 < k < n and axis[k] < 0.5 <= axis[k - 1]:
+            xf = xs[k - 1] + (axis[k - 1] - 0.5) / (axis[k - 1] - axis[k]) * dx
+        else:
+            xf = xs[k]
+        return {"t_Myr": t_myr, "ifront_x_kpc": xf / ri.KPC,
+                "ifront_rel_clump_centre_over_lS": (xf / ri.KPC - 5.0) / 0.78,
+                "clump_mean_xHII": float(x[inside].mean()), "clump_mean_T": float(T[inside].mean()),
+                "shadow_xHII": float(x[n // 2, n // 2, int(6.3 * ri.KPC / dx)]),
+                "beside_xHII": float(x[n // 2, int(1.0 * ri.KPC / dx), int(6.3 * ri.KPC / dx)])}
+
+    print(f"# shadow clump 128^3: {targets[-1]} steps of {dt:.4g} s", file=sys.stderr, flush=True)
+    ctx.step(dt, 10)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    done, snaps, wall = 10, [], 0.0
+    chunk = 1000
+    for tgt, m in zip(targets, marks):
+        while done < tgt:
+            k = min(chunk, tgt - done)
+            t0 = time.perf_counter()
+            ctx.step(dt, k)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            done += k
+            print(f"# step {done} / {targets[-1]}", file=sys.stderr, flush=True)
+        snaps.append(snapshot(m))
+    s = ctx.stats()
+    timed = done - 10
+    cgu = w.ncell * w.spectrum.M * timed / wall
+    print(json.dumps({"metric": "RT cell-group updates/s, Iliev test 3 (shadow) at 128^3 x 3 groups", "value": cgu,
+                      "unit": "cell-group updates/s", "n_gpus": 1, "steps": timed, "warmup": 10,
+                      "ms_per_step": wall * 1e3 / timed, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "Iliev test 3 on a uniform 128^3 grid: 6.6 kpc, n_H 2e-4 / clump 4e-2, "
+                                             "F = 1e6 s^-1 cm^-2 from x = 0, HLL, 3 groups, c_r = c/10, FP64"},
+                      "substeps_per_cell_step": s["substeps_total"] / (w.ncell * timed),
+                      "attempts_max": s["attempts_max"], "flags": s["flags"], "snapshots": snaps}), flush=True)
+
+
 def bench_batch(args):
     """The batching form: 64 periodic boxes (sides 16-96, 1-3 groups, uniform
     densities, 1-8 sources; FP32 transport, FP64 chemistry, GLF), advanced as
@@ -313,6 +388,8 @@ def main():
         sys.exit(2)
     if args.form == "batch":
         return bench_batch(args)
+    if args.form == "shadow":
+        return bench_shadow(args)
     if args.form == "adjoint":
         a = adjoint_cost()
         print(json.dumps({"metric": "adjoint/forward cost ratio (checkpointed forward + reverse sweep over plain "
