@@ -187,8 +187,9 @@ class OracleRT:
         o.group_frac = frac[: w.spectrum.M].copy()
         return o
 
-    def courant_dt(self, courant=0.8):
-        return lib().or_courant_dt(self.dx, self.c_r, float(courant))
+    def courant_dt(self, courant=0.8, a=1.0):
+        """Courant step of the physical cell a dx (Sec. 4.1; a = 1: static)."""
+        return lib().or_courant_dt(a * self.dx, self.c_r, float(courant))
 
     def source_rates(self, ndot_total):
         """Per-group emission rates (K, M) by the group photon fractions."""
@@ -236,11 +237,48 @@ class OracleRT:
             return flags, nacc, natt
         return flags
 
-    def step(self, st, dt, ijk=None, ndot=None, want_counts=False, smooth=False):
+    def step(self, st, dt, ijk=None, ndot=None, want_counts=False, smooth=False, a=1.0):
         """Operator-split RT step of Sec. 3: injection, transport, thermochemistry.
         With smooth (Sec. 4.4) the chemistry starts from the state before
         injection and transport and takes their effect as constant rates
-        (eqs. smoothrate1, smoothrate2)."""
+        (eqs. smoothrate1, smoothrate2).  With a != 1 the state holds the
+        super-comoving variables of Sec. 5.4 (a^3 N, a^4 F, a^3 n_H on a grid
+        of comoving width dx): the step converts them to physical ones, takes
+        the physical step on cells of width a dx with the Compton term at a,
+        and converts back."""
+        if a != 1.0:
+            return self._comoving_step(st, dt, ijk, ndot, want_counts, smooth, a)
+        return self._step(st, dt, ijk, ndot, want_counts, smooth)
+
+    def _comoving_step(self, st, dt, ijk, ndot, want_counts, smooth, a):
+        a3, a4 = a ** 3, a ** 4
+        p = self.p
+        saved = (p.dx, p.a_exp, [[p.inflow[f][g] for g in range(3)] for f in range(6)])
+        phys = dict(st)
+        phys["N"] = st["N"] / a3
+        phys["F"] = st["F"] / a4
+        phys["nH"] = st["nH"] / a3
+        try:
+            p.dx = a * saved[0]
+            p.a_exp = a
+            for f in range(6):
+                for g in range(3):
+                    p.inflow[f][g] = saved[2][f][g] / a4
+            self.dx = p.dx
+            r = self._step(phys, dt, ijk, ndot, want_counts, smooth)
+        finally:
+            p.dx, p.a_exp = saved[0], saved[1]
+            for f in range(6):
+                for g in range(3):
+                    p.inflow[f][g] = saved[2][f][g]
+            self.dx = p.dx
+        for k in ("xHII", "xHeII", "xHeIII", "T"):
+            st[k] = phys[k]
+        st["N"] = phys["N"] * a3
+        st["F"] = phys["F"] * a4
+        return r
+
+    def _step(self, st, dt, ijk=None, ndot=None, want_counts=False, smooth=False):
         if smooth:
             N0 = st["N"].copy()
             F0 = st["F"].copy()
