@@ -208,7 +208,18 @@ rt_status rt_set_sources(rt_ctx *ctx, int n, const int32_t *ijk, const double *n
  * RT_EINVAL for another face kind or a negative or non-finite flux. */
 rt_status rt_set_inflow(rt_ctx *ctx, int face, const double *flux);
 
-/* Courant-limited step dt = courant * dx / (3 c_r) (Sec. 4.1, eq.
+/* Super-comoving RT variables (Sec. 5.4) at expansion factor a > 0 (1: a
+ * static box, the default).  With a != 1 the state arrays hold N~ = a^3 N,
+ * F~ = a^4 F (the paper's variables in units with H_0 L = 1) and a^3 n_H,
+ * and dx is the comoving cell width; the inflow fluxes of rt_set_inflow are
+ * F~ as well.  The transport runs with light speed a c_r over dt / a^2, the
+ * chemistry on N, n_H, and the Compton term at a (this sets rt_params.a_exp
+ * to a); dt stays the physical step, at most a dx / (3 c_r).  Between calls
+ * the caller may change a: N~, F~ held fixed dilute N as a^-3 and F as
+ * a^-4.  Synchronises the stream.  The adjoint needs a = 1. */
+rt_status rt_set_expansion(rt_ctx *ctx, double a);
+
+/* Courant-limited step dt = courant * a dx / (3 c_r) (Sec. 4.1, eq.
  * dt_courant, with the factor 0.8 of the paper's tests). */
 rt_status rt_courant_dt(const rt_ctx *ctx, double courant, double *dt);
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
     "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint", "rt_set_accounting",
-    "rt_set_inflow",
+    "rt_set_inflow", "rt_set_expansion",
 ]
 
 
@@ -133,6 +133,8 @@ def lib():
     L.rt_set_accounting.restype = st
     L.rt_set_inflow.argtypes = [vp, ctypes.c_int, dp]
     L.rt_set_inflow.restype = st
+    L.rt_set_expansion.argtypes = [vp, ctypes.c_double]
+    L.rt_set_expansion.restype = st
     L.rt_group_attributes.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp]
     L.rt_group_attributes.restype = st
     L.rt_hll_table.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int),

@@ -41,6 +41,8 @@ struct rt_ctx {
     double *src_prev = nullptr;
     int sm_phase = 0;
     bool sm_injected = false;
+    // expansion factor of the super-comoving state (Sec. 5.4); 1: static box
+    double a_cosmo = 1.0;
     DevStats *dstats = nullptr;
     RedOut *dred = nullptr;
     unsigned qcap = 0;               // chemistry queue capacity (cells)
@@ -586,7 +588,21 @@ extern "C" rt_status rt_set_tuning(rt_ctx *c, int head_attempts, long long queue
 extern "C" rt_status rt_courant_dt(const rt_ctx *c, double courant, double *dt)
 {
     if (!c || !dt || !(courant > 0)) return RT_EINVAL;
-    *dt = courant * c->grid.dx / (3.0 * c->groups.c_r);
+    *dt = courant * c->a_cosmo * c->grid.dx / (3.0 * c->groups.c_r);
+    return RT_OK;
+}
+
+// largest step the transport allows: the physical cell a dx over 3 c_r
+static double dt_limit(const rt_ctx *c) { return c->a_cosmo * c->grid.dx / (3.0 * c->groups.c_r); }
+
+extern "C" rt_status rt_set_expansion(rt_ctx *c, double a)
+{
+    if (!c) return RT_EINVAL;
+    if (!(a > 0) || !std::isfinite(a)) RT_FAIL(c, RT_EINVAL, "a must be positive and finite");
+    RT_HIP(c, hipStreamSynchronize(c->stream));
+    c->a_cosmo = a;
+    c->kchem.a_exp = a;
+    RT_HIP(c, hipMemcpy(c->dkchem, &c->kchem, sizeof(KChem), hipMemcpyHostToDevice));
     return RT_OK;
 }
 
@@ -618,13 +634,15 @@ static rt_status do_inject(rt_ctx *c, double dt)
 
 static rt_status do_transport(rt_ctx *c, double dt)
 {
-    const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
-    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    const double dtmax = dt_limit(c);
+    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit a dx/(3 c_r) = %g", dt, dtmax);
     if (c->params.smooth && c->sm_phase == 2)
         RT_FAIL(c, RT_ESTATE, "smoothed RT: the step's transport has run; its thermochemistry comes next");
     const int s = c->cur, d = 1 - c->cur;
     rt_status r = timed(c, TM_TRANSPORT, [&]() -> rt_status {
-        RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, c->groups.c_r, dt, c->st.N[s],
+        // super-comoving variables: light speed a c_r over dt / a^2 (Sec. 5.4)
+        const double a = c->a_cosmo;
+        RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, a * c->groups.c_r, dt / (a * a), c->st.N[s],
                                    c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth,
                                    c->acct ? acct_part(c) : nullptr, c->stream));
         return RT_OK;
@@ -655,7 +673,7 @@ static rt_status acct_close(rt_ctx *c, double dt)
     rt_status r = acct_reduce(c);
     if (r != RT_OK) return r;
     RT_HIP(c, launch_ledger(c->acct_pending ? 2 : 1, acct_part(c), acct_blocks(c->grid.ncell), c->groups.M, V,
-                            dt * c->grid.dx * c->grid.dx, c->dred, c->dstats, c->stream));
+                            dt / (c->a_cosmo * c->a_cosmo) * c->grid.dx * c->grid.dx, c->dred, c->dstats, c->stream));
     c->acct_pending = false;
     return RT_OK;
 }
@@ -692,7 +710,7 @@ static rt_status do_chem(rt_ctx *c, double dt)
         rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
             RT_HIP(c, launch_chem(part, c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
                                   c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, q,
-                                  c->head_attempts, hist, sm, c->dstats, c->stream));
+                                  c->head_attempts, hist, sm, c->a_cosmo, c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
@@ -704,8 +722,8 @@ static rt_status do_chem(rt_ctx *c, double dt)
 // destination set), then the queued cells
 static rt_status do_fused(rt_ctx *c, double dt)
 {
-    const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
-    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    const double dtmax = dt_limit(c);
+    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit a dx/(3 c_r) = %g", dt, dtmax);
     const int s = c->cur, d = 1 - c->cur;
     SmoothArgs sa;
     if (c->params.smooth) {
@@ -721,7 +739,7 @@ static rt_status do_fused(rt_ctx *c, double dt)
                                         c->st.N[d], c->st.F[d], c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T,
                                         c->st.nH, c->st.nacc, c->st.natt, c->hll_dev, c->nf, c->nth, q,
                                         c->head_attempts, c->acct ? acct_part(c) : nullptr,
-                                        c->acct ? c->dstats->hist : nullptr, sm, c->dstats, c->stream));
+                                        c->acct ? c->dstats->hist : nullptr, sm, c->a_cosmo, c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
@@ -760,7 +778,7 @@ extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
 {
     if (!c) return RT_EINVAL;
     if (nsteps < 0) RT_FAIL(c, RT_EINVAL, "nsteps < 0");
-    if (!(dt > 0)) dt = 0.8 * c->grid.dx / (3.0 * c->groups.c_r);
+    if (!(dt > 0)) dt = 0.8 * dt_limit(c);
     rt_status r = check_ready(c, dt);
     if (r != RT_OK) return r;
     for (int k = 0; k < nsteps; ++k) {
@@ -867,10 +885,11 @@ static rt_status adj_supported(rt_ctx *c, double dt)
     if (c->fp32) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs RT_PREC_FP64");
     if (c->params.smooth) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs smooth = 0");
     if (!c->params.otsa) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the on-the-spot approximation (otsa = 1)");
+    if (c->a_cosmo != 1.0) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs a static box (expansion factor 1)");
     for (int f = 0; f < 6; ++f)
         if (c->grid.bc[f] != RT_BC_PERIODIC) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs periodic boundaries");
-    const double dtmax = c->grid.dx / (3.0 * c->groups.c_r);
-    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit dx/(3 c_r) = %g", dt, dtmax);
+    const double dtmax = dt_limit(c);
+    if (dt > dtmax * (1.0 + 1e-12)) RT_FAIL(c, RT_EINVAL, "dt = %g exceeds the Courant limit a dx/(3 c_r) = %g", dt, dtmax);
     return RT_OK;
 }
 

@@ -575,7 +575,7 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
     const size_t nc = io.ncell;
 #pragma unroll
     for (int g = 0; g < M; ++g) {
-        io.N[(size_t)g * nc + i] = (R)s.N[g];
+        io.N[(size_t)g * nc + i] = (R)(s.N[g] * io.a3);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const size_t j = (size_t)(3 * g + d) * nc + i;

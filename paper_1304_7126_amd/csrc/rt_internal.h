@@ -123,6 +123,9 @@ struct ChemIO {
     double *acct;               // transport partials (fused head), or null
     unsigned long long *hist;   // substep histogram, or null
     SmoothIn<R> sm;             // smoothed RT inputs (kernels instantiated for it)
+    // super-comoving state (a != 1): the arrays hold a^3 N and a^3 n_H, the
+    // chemistry works on N and n_H
+    double a3 = 1.0, ia3 = 1.0;
 };
 
 constexpr int TAIL_BLOCKS = 1024;
@@ -137,14 +140,14 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
 // part 1: queue reset + head pass; part 2: tail pass
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
-                       const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, DevStats *stats,
-                       hipStream_t s);
+                       const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, double a,
+                       DevStats *stats, hipStream_t s);
 
 hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, const KChem &kc, const KChem *dk, double dt, const void *Nin,
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
                              int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
-                             const SmoothArgs *sm, DevStats *stats, hipStream_t s);
+                             const SmoothArgs *sm, double a, DevStats *stats, hipStream_t s);
 
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
                 const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc,
                                                         Fin + (size_t)3 * grp * nc, c, kdx, tab, nf, nth, bout, g,
                                                         grp);
-                s.N[grp] = (double)o.n;
+                s.N[grp] = (double)o.n * io.ia3;
                 av[grp] = (double)o.n;
                 av[3 + grp] = bout;
                 io.F[(size_t)(3 * grp) * nc + i] = o.fx;
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         } else {
 #pragma unroll
             for (int grp = 0; grp < M; ++grp) {
-                s.N[grp] = (double)io.N[(size_t)grp * nc + i];
+                s.N[grp] = (double)io.N[(size_t)grp * nc + i] * io.ia3;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.F[(size_t)(3 * grp + d) * nc + i]);
             }
@@ -261,7 +261,8 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
             const int si = io.sm.map ? io.sm.map[i] : -1;
 #pragma unroll
             for (int grp = 0; grp < M; ++grp) {
-                const double nt = si >= 0 ? io.sm.prev[(size_t)si * M + grp] : (double)io.sm.N[(size_t)grp * nc + i];
+                const double nt = (si >= 0 ? io.sm.prev[(size_t)si * M + grp] : (double)io.sm.N[(size_t)grp * nc + i]) *
+                                  io.ia3;
                 s.Nr[grp] = (s.N[grp] - nt) / dt;
                 s.N[grp] = nt;
 #pragma unroll
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         s.x = io.xHII[i];
         s.y2 = io.xHeII[i];
         s.y3 = io.xHeIII[i];
-        cc = make_cc(k, io.nH[i], io.T[i]);
+        cc = make_cc(k, io.nH[i] * io.ia3, io.T[i]);
         if (chem_init<CM, V>(k, dt, cc.Tiso, fin, s)) {
             done = false;
             for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM, V>(k, cc, s, fl);
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
                     const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
                     if (p < n) {
                         cell = q_load(q, p, s);
-                        cc = make_cc(k, io.nH[cell], io.T[cell]);
+                        cc = make_cc(k, io.nH[cell] * io.ia3, io.T[cell]);
                         active = true;
                     }
                 }
@@ -411,9 +412,11 @@ static void dispatch_SM(int part, const KGrid &g, const KChem &kc, const KChem *
 template <typename R>
 static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *xHeII, double *xHeIII, double *T,
                          const double *nH, int32_t *nacc, int32_t *natt, double *acct, unsigned long long *hist,
-                         const SmoothArgs *sm, double dt)
+                         const SmoothArgs *sm, double dt, double a)
 {
     ChemIO<R> io;
+    io.a3 = a * a * a;
+    io.ia3 = 1.0 / io.a3;
     io.acct = acct;
     io.hist = hist;
     if (sm) {
@@ -438,14 +441,14 @@ static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *x
 
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
-                       const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, DevStats *stats,
-                       hipStream_t s)
+                       const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, double a,
+                       DevStats *stats, hipStream_t s)
 {
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt);
+        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a);
         dispatch_SM<float, 0, 0>(part, g, kc, dk, dt, 0.f, 0.f, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt);
+        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a);
         dispatch_SM<double, 0, 0>(part, g, kc, dk, dt, 0.0, 0.0, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     }
     return hipGetLastError();
@@ -455,21 +458,23 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
                              int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
-                             const SmoothArgs *sm, DevStats *stats, hipStream_t s)
+                             const SmoothArgs *sm, double a, DevStats *stats, hipStream_t s)
 {
-    const double kdx = dt / g.dx;
+    // super-comoving transport: light speed a c_r over dt / a^2
+    const double kdx = dt / (a * a) / g.dx;
+    const double ctr = a * kc.cr;
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt);
+        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt, a);
         if (flux)
-            dispatch_SM<float, 1, 1>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<float, 1, 1>(part, g, kc, dk, dt, (float)ctr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
-            dispatch_SM<float, 1, 0>(part, g, kc, dk, dt, (float)kc.cr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<float, 1, 0>(part, g, kc, dk, dt, (float)ctr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt);
+        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt, a);
         if (flux)
-            dispatch_SM<double, 1, 1>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<double, 1, 1>(part, g, kc, dk, dt, ctr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
-            dispatch_SM<double, 1, 0>(part, g, kc, dk, dt, kc.cr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
+            dispatch_SM<double, 1, 0>(part, g, kc, dk, dt, ctr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
     }
     return hipGetLastError();
 }

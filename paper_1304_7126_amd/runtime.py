@@ -231,6 +231,11 @@ class RTContext:
         f = np.ascontiguousarray(np.asarray(flux, np.float64).reshape(self.M))
         check(lib().rt_set_inflow(self._h, int(face), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._h)
 
+    def set_expansion(self, a):
+        """Super-comoving variables at expansion factor a (Sec. 5.4): the
+        radiation arrays hold a^3 N and a^4 F, nH holds a^3 n_H."""
+        check(lib().rt_set_expansion(self._h, float(a)), self._h)
+
     def set_accounting(self, enabled=True):
         """Photon accounting (injected, absorbed, outflow, substep histogram)."""
         check(lib().rt_set_accounting(self._h, int(bool(enabled))), self._h)
