@@ -29,9 +29,9 @@ VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 # 101-105), valid for the kernel sources they were taken with
 # (profiles/k_head_fused_256cube_3grp_pmc_bytes.md and _pmc_valu.md).
 KERNEL_SOURCES = ("rt_kernels.hip", "rt_cell.h", "rt_device.h", "rt_internal.h")
-COUNTERS_SOURCE_HASH = "242414a62d18fce1"
-COUNTERS = {"read_bytes": 2641281 * 2 * 1024, "write_bytes": 3159533 * 1024, "valu_wave_instr": 3.3145e9,
-            "lane_util": 0.676, "fp64_flops_all_lanes": 1.166e11, "ms": 5.839}
+COUNTERS_SOURCE_HASH = "df1e28ab453462dd"
+COUNTERS = {"read_bytes": 2717837 * 2 * 1024, "write_bytes": 3344772 * 1024, "valu_wave_instr": 3.3297e9,
+            "lane_util": 0.678, "fp64_flops_all_lanes": 1.167e11, "ms": 5.984}
 
 
 def kernel_source_hash():
@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--smooth-steps", type=int, default=30,
                     help="timed steps of the smoothed-vs-plain comparison at floor 1e-12 and of the "
                          "with/without OTSA comparison (0: skip both)")
+    ap.add_argument("--expansion", type=float, default=1.0,
+                    help="time the step with super-comoving variables at this expansion factor (Sec. 5.4)")
     ap.add_argument("--no-otsa", action="store_true",
                     help="time the step without the on-the-spot approximation (Sec. 3.3.2) instead")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -111,7 +113,8 @@ def cpu_baseline(seconds, n_full, M):
                       f"from the initial state, {el:.1f} s wall"}
 
 
-def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, floor=0.0, nH_mean=1e-3, otsa=True):
+def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, floor=0.0, nH_mean=1e-3, otsa=True,
+             a=1.0):
     """The lognormal n^3 x 3 workload: build it, run `warmup` steps, then time
     `steps` rt_step calls (injection, transport fused with the first
     chemistry pass, the compacted tail), with the library's HIP events
@@ -130,7 +133,12 @@ def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, flo
     st = ri.initial_state(w)
     ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
     ctx = RTContext.for_workload(w, fp32=fp32, smooth=smooth, N_floor=floor)
+    if a != 1.0:
+        # the same comoving box at expansion factor a: comoving densities
+        st["nH"] = st["nH"] * a ** 3
     ctx.load_state(st)
+    if a != 1.0:
+        ctx.set_expansion(a)
     ctx.set_sources(ijk, ctx.source_rates(nd))
     dt = ctx.courant_dt()
     if head_attempts > 0:
@@ -197,6 +205,16 @@ def otsa_comparison(n, fp32, flux_name, steps, warmup, head_attempts):
             "attempts_max": s["attempts_max"], "flags": s["flags"],
             "ms_per_launch": {k: r["per"][k] for k in ("inject", "head", "tail")}}
     out["time_ratio"] = out["case_A_with_emission"]["ms_per_step"] / out["otsa"]["ms_per_step"]
+    # the same comoving box at a = 1/8 (super-comoving variables, Sec. 5.4):
+    # 512x denser gas in physical units, photons in a^3 N
+    a = 0.125
+    r = grid_run(n, fp32, flux_name, steps, warmup, head_attempts, a=a)
+    s = r["stats"]
+    nc = r["w"].ncell
+    out["super_comoving_a_0.125"] = {
+        "value": r["cgu"], "unit": "cell-group updates/s", "ms_per_step": r["ms"],
+        "substeps_per_cell_step": s["substeps_total"] / (nc * steps), "attempts_max": s["attempts_max"],
+        "flags": s["flags"], "ms_per_launch": {k: r["per"][k] for k in ("inject", "head", "tail")}}
     return out
 
 
@@ -405,7 +423,7 @@ def main():
     n = args.n
     floor = args.n_floor if args.n_floor is not None else (1e-12 if args.smooth else 0.0)
     r = grid_run(n, fp32, args.flux, args.steps, args.warmup, args.head_attempts, args.smooth, floor,
-                 otsa=not args.no_otsa)
+                 otsa=not args.no_otsa, a=args.expansion)
     w, M, K, s, ms, cgu, per = r["w"], r["M"], args.steps, r["stats"], r["ms"], r["cgu"], r["per"]
 
     rad, gas = algorithmic_bytes(M, fp32)
@@ -416,7 +434,7 @@ def main():
     t_head = per["head"]
     achieved = step_bytes / (t_head * 1e-3) / 1e9
     counters_valid = (kernel_source_hash() == COUNTERS_SOURCE_HASH and fp32 and n == 256 and args.flux == "hll"
-                      and not args.smooth and floor == 0.0 and not args.no_otsa)
+                      and not args.smooth and floor == 0.0 and not args.no_otsa and args.expansion == 1.0)
     traffic = COUNTERS["read_bytes"] + COUNTERS["write_bytes"] if counters_valid else None
     # the kernel is bound by its VALU issue rate: counter figures (static,
     # from the profile) and the live duration
@@ -439,6 +457,8 @@ def main():
         wl += f"{', smoothed RT' if args.smooth else ''}, N_floor={floor:g}"
     if args.no_otsa:
         wl += ", no OTSA (case A, recombination photons)"
+    if args.expansion != 1.0:
+        wl += f", super-comoving at a={args.expansion:g}"
     out = {
         "metric": "RT cell-group updates/s at 256^3 x 3 groups; adjoint/forward cost ratio",
         "value": cgu,
@@ -462,7 +482,7 @@ def main():
         "roofline": roof,
     }
     torch.cuda.empty_cache()
-    if args.smooth_steps > 0 and not args.smooth and not args.no_otsa:
+    if args.smooth_steps > 0 and not args.smooth and not args.no_otsa and args.expansion == 1.0:
         out["smoothing"] = smoothing_comparison(n, fp32, args.flux, args.smooth_steps, args.warmup,
                                                 args.head_attempts)
         torch.cuda.empty_cache()
