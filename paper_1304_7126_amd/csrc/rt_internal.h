@@ -95,14 +95,18 @@ hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c
 hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, int M, double V, double dtdx2,
                          const RedOut *red, DevStats *st, hipStream_t s);
 
-// queue of cells still subcycling after the head pass (caller scratch)
+// queue of cells still subcycling after the head pass (caller scratch):
+// cells predicted to need many more substeps fill [0, cap_h) from the front
+// (count_h), the others [cap_h, cap) (count); the tail takes the former first
 struct QueueView {
-    unsigned *count;  // [0] cells queued, [1] (head) cells taken by the tail
+    unsigned *count;    // [0] cells in the second region, [1] (head) cells taken by the tail, [32] (count_h)
     unsigned *head;
+    unsigned *count_h;  // cells in the first region
     int32_t *cell, *acc, *att;
-    double *v;        // QV (smoothed RT: QV_SMOOTH) planes of `stride` doubles
-    unsigned cap;     // cells the head pass may queue
-    unsigned stride;  // plane length of the layout
+    double *v;          // QV (smoothed RT: QV_SMOOTH) planes of `stride` doubles
+    unsigned cap;       // cells the head pass may queue
+    unsigned cap_h;     // size of the first region
+    unsigned stride;    // plane length of the layout
 };
 
 template <typename R>

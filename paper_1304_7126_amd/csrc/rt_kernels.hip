@@ -281,22 +281,41 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         }
     }
     if (FUSE && io.acct) block_acct(io.acct, av);
-    // wave-aggregated enqueue of the unfinished cells
+    // wave-aggregated enqueue of the unfinished cells.  A cell that has not
+    // accepted a substep in its K attempts (a front cell whose state changes
+    // fast) usually needs many more: such cells go to the front region,
+    // which the tail works off first, so that the longest sequential chains
+    // start early instead of draining the tail at its end.
     const bool want = !done;
-    const unsigned long long m = __ballot(want);
-    bool queued = false;
+    const bool heavy = want && s.acc == 0;
+    unsigned p = ~0u;
+    const unsigned long long mh = __ballot(heavy);
+    if (mh) {
+        const int leader = __ffsll((long long)mh) - 1;
+        unsigned base = 0;
+        if (lane_id() == leader) base = atomicAdd(q.count_h, (unsigned)__popcll(mh));
+        base = __shfl(base, leader);
+        if (heavy) {
+            const unsigned ph = base + (unsigned)__popcll(mh & ((1ull << lane_id()) - 1ull));
+            if (ph < q.cap_h) p = ph;
+        }
+    }
+    const bool rest = want && p == ~0u;
+    const unsigned long long m = __ballot(rest);
     if (m) {
         const int leader = __ffsll((long long)m) - 1;
         unsigned base = 0;
         if (lane_id() == leader) base = atomicAdd(q.count, (unsigned)__popcll(m));
         base = __shfl(base, leader);
-        if (want) {
-            const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
-            if (p < q.cap) {
-                q_store(q, p, i, s);
-                queued = true;
-            }
+        if (rest) {
+            const unsigned pl = q.cap_h + base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+            if (pl < q.cap) p = pl;
         }
+    }
+    bool queued = false;
+    if (p != ~0u) {
+        q_store(q, p, i, s);
+        queued = true;
     }
     if (want && !queued) {
         while (!done) done = chem_attempt<CM, V>(k, cc, s, fl);
@@ -321,7 +340,9 @@ template <typename R, int M, int V>
 __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
-    const unsigned n = min(*q.count, q.cap);
+    // front region (predicted long chains) first, then the rest
+    const unsigned nh = min(*q.count_h, q.cap_h);
+    const unsigned n = nh + min(*q.count, q.cap - q.cap_h);
     std::conditional_t<(V & V_SMOOTH) != 0, CSR, CS> s;
     uint32_t cell = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
@@ -341,9 +362,9 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
                 base = __shfl(base, leader);
                 if (base >= n) exhausted = true;
                 if (need) {
-                    const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
-                    if (p < n) {
-                        cell = q_load(q, p, s);
+                    const unsigned t = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+                    if (t < n) {
+                        cell = q_load(q, t < nh ? t : q.cap_h + (t - nh), s);
                         cc = make_cc(k, io.nH[cell] * io.ia3, io.T[cell]);
                         active = true;
                     }
@@ -379,7 +400,7 @@ static void launch_head_tail(int part, const KGrid &g, const KChem &kc, const KC
                              const QueueView &q, int K, DevStats *st, hipStream_t s)
 {
     if (part == 1) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 2);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 33);
         hipLaunchKernelGGL((k_head<R, M, FUSE, FLUX, V>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g,
                            dk, dt, c, kdx, (const R *)Nin, (const R *)Fin, io, (const R *)tab, nf, nth, q, K, st);
     } else {
@@ -497,6 +518,7 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
     QueueView q;
     q.count = (unsigned *)b;
     q.head = q.count + 1;
+    q.count_h = q.count + 32;  // its own 128-byte line: the two enqueue atomics do not share one
     b += 256;
     q.cell = (int32_t *)b;
     q.acc = q.cell + layout_cap;
@@ -504,6 +526,7 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
     b += align256((size_t)layout_cap * 3 * sizeof(int32_t));
     q.v = (double *)b;
     q.cap = cap;
+    q.cap_h = cap / 4;
     q.stride = layout_cap;
     return q;
 }
