@@ -139,8 +139,10 @@ typedef struct {
  *   nacc, natt  optional int32 per-cell counters of accepted substeps and
  *         of attempts in the last thermochemistry pass (NULL: not written)
  *   scratch  device buffer of at least rt_scratch_bytes() bytes: reduction
- *         partials and the queue of cells still subcycling after the first
- *         chemistry pass.  Required. */
+ *         partials, the queue of cells still subcycling after the first
+ *         chemistry pass, accounting partials and each cell's attempt count
+ *         of the previous pass (which orders the queue; rt_bind clears it).
+ *         Required; the library owns its contents while it is bound. */
 typedef struct {
     void *N[2];
     void *F[2];

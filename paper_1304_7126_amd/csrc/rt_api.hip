@@ -442,10 +442,13 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     return RT_OK;
 }
 
+// per-cell attempt counts of the previous chemistry pass (one byte per cell)
+static size_t prev_att_bytes(const rt_ctx *c) { return (c->grid.ncell + 255) & ~(size_t)255; }
+
 static size_t scratch_need(const rt_ctx *c)
 {
     return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max, c->params.smooth != 0) +
-           acct_bytes(c->grid.ncell);
+           acct_bytes(c->grid.ncell) + prev_att_bytes(c);
 }
 
 // accounting partials: after the reduction partials and the queue
@@ -454,6 +457,9 @@ static double *acct_part(const rt_ctx *c)
     return (double *)((char *)c->st.scratch + ((reduction_scratch_bytes() + 255) & ~(size_t)255) +
                       queue_bytes(c->qcap_max, c->params.smooth != 0));
 }
+
+// previous-pass attempt counts: after the accounting partials
+static uint8_t *prev_att(const rt_ctx *c) { return (uint8_t *)acct_part(c) + acct_bytes(c->grid.ncell); }
 
 extern "C" size_t rt_scratch_bytes(const rt_ctx *c)
 {
@@ -474,6 +480,8 @@ extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
     c->bound = true;
     c->cur = 0;
     c->sm_phase = 0;
+    // no previous pass yet: every count starts at zero
+    RT_HIP(c, hipMemset(prev_att(c), 0, c->grid.ncell));
     return RT_OK;
 }
 
@@ -710,7 +718,7 @@ static rt_status do_chem(rt_ctx *c, double dt)
         rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
             RT_HIP(c, launch_chem(part, c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
                                   c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc, c->st.natt, q,
-                                  c->head_attempts, hist, sm, c->a_cosmo, c->dstats, c->stream));
+                                  c->head_attempts, hist, sm, c->a_cosmo, prev_att(c), c->dstats, c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;
@@ -739,7 +747,8 @@ static rt_status do_fused(rt_ctx *c, double dt)
                                         c->st.N[d], c->st.F[d], c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T,
                                         c->st.nH, c->st.nacc, c->st.natt, c->hll_dev, c->nf, c->nth, q,
                                         c->head_attempts, c->acct ? acct_part(c) : nullptr,
-                                        c->acct ? c->dstats->hist : nullptr, sm, c->a_cosmo, c->dstats, c->stream));
+                                        c->acct ? c->dstats->hist : nullptr, sm, c->a_cosmo, prev_att(c), c->dstats,
+                                        c->stream));
             return RT_OK;
         });
         if (r != RT_OK) return r;

@@ -482,6 +482,13 @@ __device__ __forceinline__ double chem_finish(const KChem &k, const CC &cc, cons
 // state {N[3], fs[3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}, followed with
 // smoothed RT by {Nr[3], fb[3]}.
 constexpr int QV = 12;
+
+// a queued cell that took at least this many attempts in the previous pass
+// goes to the tail's first region
+#ifndef RT_TAIL_LONG_ATTEMPTS
+#define RT_TAIL_LONG_ATTEMPTS 48
+#endif
+constexpr int TAIL_LONG_ATTEMPTS = RT_TAIL_LONG_ATTEMPTS;
 constexpr int QV_SMOOTH = 18;
 
 __device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CS &) {}
@@ -589,6 +596,7 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
     io.T[i] = T;
     if (io.nacc) io.nacc[i] = s.acc;
     if (io.natt) io.natt[i] = s.att;
+    if (io.prev_att) io.prev_att[i] = (uint8_t)(s.att < 255 ? s.att : 255);
 }
 
 }  // namespace rtm1

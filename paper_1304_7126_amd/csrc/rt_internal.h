@@ -95,17 +95,18 @@ hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c
 hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, int M, double V, double dtdx2,
                          const RedOut *red, DevStats *st, hipStream_t s);
 
-// queue of cells still subcycling after the head pass (caller scratch):
-// cells predicted to need many more substeps fill [0, cap_h) from the front
-// (count_h), the others [cap_h, cap) (count); the tail takes the former first
+// queue of cells still subcycling after the head pass (caller scratch), in
+// three regions the tail works off in order: cells that took many attempts
+// in the previous pass, cells that accepted no substep in this one's first
+// attempts, the rest.  A region that is full passes its cells to the next.
 struct QueueView {
-    unsigned *count;    // [0] cells in the second region, [1] (head) cells taken by the tail, [32] (count_h)
+    unsigned *count;    // the counter block: [0] region 2, [1] cells taken by the tail, [32] region 1, [64] region 0
     unsigned *head;
-    unsigned *count_h;  // cells in the first region
+    unsigned *cnt[3];   // cells queued per region (each on its own cache line)
+    unsigned rbeg[3], rlen[3];  // region offsets and sizes
     int32_t *cell, *acc, *att;
     double *v;          // QV (smoothed RT: QV_SMOOTH) planes of `stride` doubles
     unsigned cap;       // cells the head pass may queue
-    unsigned cap_h;     // size of the first region
     unsigned stride;    // plane length of the layout
 };
 
@@ -130,6 +131,9 @@ struct ChemIO {
     // super-comoving state (a != 1): the arrays hold a^3 N and a^3 n_H, the
     // chemistry works on N and n_H
     double a3 = 1.0, ia3 = 1.0;
+    // attempts of each cell in the previous chemistry pass (capped at 255),
+    // read to order the tail and rewritten; null: not kept
+    uint8_t *prev_att = nullptr;
 };
 
 constexpr int TAIL_BLOCKS = 1024;
@@ -145,13 +149,13 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
                        const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, double a,
-                       DevStats *stats, hipStream_t s);
+                       uint8_t *prev_att, DevStats *stats, hipStream_t s);
 
 hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, const KChem &kc, const KChem *dk, double dt, const void *Nin,
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
                              int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
-                             const SmoothArgs *sm, double a, DevStats *stats, hipStream_t s);
+                             const SmoothArgs *sm, double a, uint8_t *prev_att, DevStats *stats, hipStream_t s);
 
 hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, const void *N, const void *F,
                          const double *xHII, const double *nH, void *scratch, RedOut *dev_out,

@@ -281,35 +281,29 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         }
     }
     if (FUSE && io.acct) block_acct(io.acct, av);
-    // wave-aggregated enqueue of the unfinished cells.  A cell that has not
-    // accepted a substep in its K attempts (a front cell whose state changes
-    // fast) usually needs many more: such cells go to the front region,
-    // which the tail works off first, so that the longest sequential chains
-    // start early instead of draining the tail at its end.
+    // wave-aggregated enqueue of the unfinished cells, by expected length of
+    // their chain of substeps: cells that took many attempts in the previous
+    // pass (the fronts move little in a step), then cells that accepted no
+    // substep in their K attempts here (a state that changes fast), then the
+    // rest.  The tail works the regions off in this order, so that the
+    // longest chains start first instead of draining the tail at its end.
     const bool want = !done;
-    const bool heavy = want && s.acc == 0;
+    const int cls = !want ? 3
+                          : (io.prev_att && io.prev_att[i] >= TAIL_LONG_ATTEMPTS) ? 0 : (s.acc == 0 ? 1 : 2);
     unsigned p = ~0u;
-    const unsigned long long mh = __ballot(heavy);
-    if (mh) {
-        const int leader = __ffsll((long long)mh) - 1;
-        unsigned base = 0;
-        if (lane_id() == leader) base = atomicAdd(q.count_h, (unsigned)__popcll(mh));
-        base = __shfl(base, leader);
-        if (heavy) {
-            const unsigned ph = base + (unsigned)__popcll(mh & ((1ull << lane_id()) - 1ull));
-            if (ph < q.cap_h) p = ph;
-        }
-    }
-    const bool rest = want && p == ~0u;
-    const unsigned long long m = __ballot(rest);
-    if (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        unsigned base = 0;
-        if (lane_id() == leader) base = atomicAdd(q.count, (unsigned)__popcll(m));
-        base = __shfl(base, leader);
-        if (rest) {
-            const unsigned pl = q.cap_h + base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
-            if (pl < q.cap) p = pl;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const bool cand = want && p == ~0u && cls <= r;  // a full region passes its cells on
+        const unsigned long long m = __ballot(cand);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            unsigned base = 0;
+            if (lane_id() == leader) base = atomicAdd(q.cnt[r], (unsigned)__popcll(m));
+            base = __shfl(base, leader);
+            if (cand) {
+                const unsigned k = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+                if (k < q.rlen[r]) p = q.rbeg[r] + k;
+            }
         }
     }
     bool queued = false;
@@ -340,19 +334,22 @@ template <typename R, int M, int V>
 __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
-    // front region (predicted long chains) first, then the rest
-    const unsigned nh = min(*q.count_h, q.cap_h);
-    const unsigned n = nh + min(*q.count, q.cap - q.cap_h);
+    // the regions in order: longest expected chains first
+    const unsigned n0 = min(*q.cnt[0], q.rlen[0]);
+    const unsigned n1 = min(*q.cnt[1], q.rlen[1]);
+    const unsigned n = n0 + n1 + min(*q.cnt[2], q.rlen[2]);
     std::conditional_t<(V & V_SMOOTH) != 0, CSR, CS> s;
     uint32_t cell = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
+    bool raised = false;
     unsigned fl = 0;
     unsigned long long a_acc = 0, a_att = 0, a_max = 0;
     __shared__ unsigned s_hist[64];
     if (io.hist) hist_init(s_hist);
     while (true) {
         if (!exhausted) {
+            bool first = false;
             const bool need = !active;
             const unsigned long long m = __ballot(need);
             if (m) {
@@ -364,11 +361,19 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
                 if (need) {
                     const unsigned t = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
                     if (t < n) {
-                        cell = q_load(q, t < nh ? t : q.cap_h + (t - nh), s);
+                        const unsigned pos = t < n0 ? t : (t < n0 + n1 ? q.rbeg[1] + (t - n0) : q.rbeg[2] + (t - n0 - n1));
+                        cell = q_load(q, pos, s);
                         cc = make_cc(k, io.nH[cell] * io.ia3, io.T[cell]);
                         active = true;
+                        first = t < n0;
                     }
                 }
+            }
+            // a wave holding cells of the first region (the longest chains)
+            // issues ahead of the others for the rest of its life
+            if (!raised && __any(first)) {
+                __builtin_amdgcn_s_setprio(3);
+                raised = true;
             }
         }
         if (!__any(active)) break;
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
 
 __global__ void k_zero_u32(unsigned *p, int n)
 {
-    if (threadIdx.x < (unsigned)n) p[threadIdx.x] = 0u;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0u;
 }
 
 // part 1: reset the queue counters and run the head pass; part 2: the tail
@@ -400,7 +405,7 @@ static void launch_head_tail(int part, const KGrid &g, const KChem &kc, const KC
                              const QueueView &q, int K, DevStats *st, hipStream_t s)
 {
     if (part == 1) {
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 33);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 65);
         hipLaunchKernelGGL((k_head<R, M, FUSE, FLUX, V>), dim3((unsigned)((g.ncell + 255) / 256)), dim3(256), 0, s, g,
                            dk, dt, c, kdx, (const R *)Nin, (const R *)Fin, io, (const R *)tab, nf, nth, q, K, st);
     } else {
@@ -433,9 +438,10 @@ static void dispatch_SM(int part, const KGrid &g, const KChem &kc, const KChem *
 template <typename R>
 static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *xHeII, double *xHeIII, double *T,
                          const double *nH, int32_t *nacc, int32_t *natt, double *acct, unsigned long long *hist,
-                         const SmoothArgs *sm, double dt, double a)
+                         const SmoothArgs *sm, double dt, double a, uint8_t *prev_att)
 {
     ChemIO<R> io;
+    io.prev_att = prev_att;
     io.a3 = a * a * a;
     io.ia3 = 1.0 / io.a3;
     io.acct = acct;
@@ -463,13 +469,15 @@ static ChemIO<R> make_io(size_t ncell, void *N, void *F, double *xHII, double *x
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,
                        double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc, int32_t *natt,
                        const QueueView &q, int K, unsigned long long *hist, const SmoothArgs *sm, double a,
-                       DevStats *stats, hipStream_t s)
+                       uint8_t *prev_att, DevStats *stats, hipStream_t s)
 {
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a);
+        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a,
+                                          prev_att);
         dispatch_SM<float, 0, 0>(part, g, kc, dk, dt, 0.f, 0.f, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a);
+        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a,
+                                            prev_att);
         dispatch_SM<double, 0, 0>(part, g, kc, dk, dt, 0.0, 0.0, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
     }
     return hipGetLastError();
@@ -479,19 +487,21 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
                              const void *Fin, void *Nout, void *Fout, double *xHII, double *xHeII, double *xHeIII,
                              double *T, const double *nH, int32_t *nacc, int32_t *natt, const void *hll, int nf,
                              int nth, const QueueView &q, int K, double *acct, unsigned long long *hist,
-                             const SmoothArgs *sm, double a, DevStats *stats, hipStream_t s)
+                             const SmoothArgs *sm, double a, uint8_t *prev_att, DevStats *stats, hipStream_t s)
 {
     // super-comoving transport: light speed a c_r over dt / a^2
     const double kdx = dt / (a * a) / g.dx;
     const double ctr = a * kc.cr;
     if (fp32) {
-        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt, a);
+        ChemIO<float> io = make_io<float>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt, a,
+                                          prev_att);
         if (flux)
             dispatch_SM<float, 1, 1>(part, g, kc, dk, dt, (float)ctr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
             dispatch_SM<float, 1, 0>(part, g, kc, dk, dt, (float)ctr, (float)kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
     } else {
-        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm, dt, a);
+        ChemIO<double> io = make_io<double>(g.ncell, Nout, Fout, xHII, xHeII, xHeIII, T, nH, nacc, natt, acct, hist, sm,
+                                            dt, a, prev_att);
         if (flux)
             dispatch_SM<double, 1, 1>(part, g, kc, dk, dt, ctr, kdx, Nin, Fin, io, hll, nf, nth, q, K, stats, s);
         else
@@ -503,13 +513,13 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
 // -------------------------------------------------------------- reductions
 size_t reduction_scratch_bytes() { return (size_t)RED_BLOCKS * sizeof(RedOut); }
 
-// scratch layout: [reduction partials][2 counters, padded to 256 B]
+// scratch layout: [reduction partials][queue counters, 512 B]
 //                 [cell, acc, att: 3 x cap int32][QV (or QV_SMOOTH) x cap doubles]
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t queue_bytes(unsigned cap, bool smooth)
 {
-    return 256 + align256((size_t)cap * 3 * sizeof(int32_t)) + (size_t)(smooth ? QV_SMOOTH : QV) * cap * sizeof(double);
+    return 512 + align256((size_t)cap * 3 * sizeof(int32_t)) + (size_t)(smooth ? QV_SMOOTH : QV) * cap * sizeof(double);
 }
 
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
@@ -518,15 +528,22 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
     QueueView q;
     q.count = (unsigned *)b;
     q.head = q.count + 1;
-    q.count_h = q.count + 32;  // its own 128-byte line: the two enqueue atomics do not share one
-    b += 256;
+    q.cnt[0] = q.count + 64;
+    q.cnt[1] = q.count + 32;
+    q.cnt[2] = q.count;
+    b += 512;
     q.cell = (int32_t *)b;
     q.acc = q.cell + layout_cap;
     q.att = q.acc + layout_cap;
     b += align256((size_t)layout_cap * 3 * sizeof(int32_t));
     q.v = (double *)b;
     q.cap = cap;
-    q.cap_h = cap / 4;
+    q.rbeg[0] = 0;
+    q.rlen[0] = cap / 16;
+    q.rbeg[1] = q.rlen[0];
+    q.rlen[1] = cap / 4;
+    q.rbeg[2] = q.rbeg[1] + q.rlen[1];
+    q.rlen[2] = cap - q.rbeg[2];
     q.stride = layout_cap;
     return q;
 }
