@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ k
         const double e5 = k.isothermal ? cc.Tiso : s.Tmu;
         const double h = s.h >= s.rem * (1.0 - 1e-10) ? s.rem : s.h;  // the length chem_attempt takes
         const int acc0 = s.acc;
-        done = chem_attempt<CM>(k, cc, s, fl);
+        done = chem_attempt<CM, 0, false>(k, cc, s, fl);  // one attempt per call: h above is its length
         if (s.acc != acc0) {
             if (fits && n < cnt) {
                 double *e = tr + TV * n;

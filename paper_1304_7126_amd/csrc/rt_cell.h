@@ -291,8 +291,12 @@ __device__ __forceinline__ bool chem_init(const KChem &k, double dt, double T, b
 // 10% check the state is unchanged and h is halved; on success the state
 // advances by h, and the next h doubles when every relative change was
 // below 5%.  Returns true when the cell has filled dt_RT (or reached the
-// attempt cap, flag bit 0).
-template <int M, int V = 0, class St>
+// attempt cap, flag bit 0).  With RETRY, attempts that fail the photon check
+// (the first stage, which depends only on the state and h) are repeated
+// with the halved h inside the call before the gas stages run: each still
+// counts as an attempt, and the sequence of attempts is the same, but a
+// lane that would sit out the rest of a failed attempt goes on at once.
+template <int M, int V = 0, bool RETRY = true, class St>
 __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s, unsigned &flags)
 {
     constexpr bool SM = (V & V_SMOOTH) != 0;
@@ -314,8 +318,7 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
     const double nHeII = y2 * nHe;
     const double nHII = x * nH;
     const double nHeIII = y3 * nHe;
-    double Nn[M], rd[M];
-    bool fail = false;
+    double Nn[M], rd[M], D[M];
     // without OTSA: photons of recombinations straight to the ground state,
     // (alpha_A - alpha_B) n_j n_e with the state at the start of the
     // substep, into the group that holds species j's threshold (eq. cool_N_cr)
@@ -330,26 +333,38 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
         for (int g = 0; g < M; ++g) Crec[g] = k.brec[g][0] * em0 + k.brec[g][1] * em1 + k.brec[g][2] * em2;
     }
 #pragma unroll
-    for (int g = 0; g < M; ++g) {
-        const double D = k.csN[g][0] * nHI + k.csN[g][1] * nHeI + k.csN[g][2] * nHeII;
-        rd[g] = 1.0 / (1.0 + h * D);
-        if constexpr (SM) {
-            // a negative rate may take the update below zero: it stops there
-            const double src = CA ? Crec[g] + s.Nr[g] : s.Nr[g];
-            const double nn = (s.N[g] + h * src) * rd[g];
-            Nn[g] = nn < 0.0 ? 0.0 : nn;
-        } else if constexpr (CA) {
-            Nn[g] = (s.N[g] + h * Crec[g]) * rd[g];
-        } else
-            Nn[g] = s.N[g] * rd[g];
-        if (s.N[g] > k.N_floor) {
-            fail |= rel_above(Nn[g], s.N[g], 0.1);
-            small &= fabs(Nn[g] - s.N[g]) < 0.05 * s.N[g];
+    for (int g = 0; g < M; ++g) D[g] = k.csN[g][0] * nHI + k.csN[g][1] * nHeI + k.csN[g][2] * nHeII;
+    for (;;) {
+        bool fail = false;
+#pragma unroll
+        for (int g = 0; g < M; ++g) {
+            rd[g] = 1.0 / (1.0 + h * D[g]);
+            if constexpr (SM) {
+                // a negative rate may take the update below zero: it stops there
+                const double src = CA ? Crec[g] + s.Nr[g] : s.Nr[g];
+                const double nn = (s.N[g] + h * src) * rd[g];
+                Nn[g] = nn < 0.0 ? 0.0 : nn;
+            } else if constexpr (CA) {
+                Nn[g] = (s.N[g] + h * Crec[g]) * rd[g];
+            } else
+                Nn[g] = s.N[g] * rd[g];
+            if (s.N[g] > k.N_floor) {
+                fail |= rel_above(Nn[g], s.N[g], 0.1);
+                small &= fabs(Nn[g] - s.N[g]) < 0.05 * s.N[g];
+            }
         }
-    }
-    if (fail) {
+        if (!fail) break;
         s.h = 0.5 * h;
-        return false;
+        if (!RETRY) return false;
+        // the next attempt, from its start
+        if (s.att >= k.max_att) {
+            flags |= 1u;
+            return true;
+        }
+        ++s.att;
+        h = s.h;
+        if (h >= s.rem * (1.0 - 1e-10)) h = s.rem;
+        small = true;
     }
     const double mu0 = mu_of(k, x, y2, y3);
     const double ne0 = nHII + (y2 + 2.0 * y3) * nHe;

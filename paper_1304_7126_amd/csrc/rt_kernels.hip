@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
         cc = make_cc(k, io.nH[i] * io.ia3, io.T[i]);
         if (chem_init<CM, V>(k, dt, cc.Tiso, fin, s)) {
             done = false;
-            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM, V>(k, cc, s, fl);
+            for (int a = 0; a < K && !done; ++a) done = chem_attempt<CM, V, false>(k, cc, s, fl);
         } else {
             fl |= 2u;
         }
