@@ -305,6 +305,7 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
     uint32_t cell = 0, box = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
+    unsigned rbase = 0, ravail = 0;  // positions this wave has reserved and not yet handed out
     unsigned fl = 0;
     unsigned long long a_acc = 0, a_att = 0, a_max = 0;
     while (true) {
@@ -312,18 +313,30 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
             const bool need = !active;
             const unsigned long long m = __ballot(need);
             if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                unsigned base = 0;
-                if (lane == leader) base = atomicAdd(q.ctr + 2, (unsigned)__popcll(m));
-                base = __shfl(base, leader);
-                if (base >= n) exhausted = true;
-                if (need) {
-                    const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-                    if (p < n) {
-                        bq_load(q, stride, p, box, cell, s);
-                        cc = make_cc(*boxes[box].kchem, boxes[box].nH[cell], boxes[box].T[cell]);
-                        active = true;
-                    }
+                // as in the grid's tail: reservations of a wave's width
+                const unsigned nneed = (unsigned)__popcll(m);
+                const unsigned r = (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+                unsigned p;
+                if (ravail >= nneed) {
+                    p = rbase + r;
+                    rbase += nneed;
+                    ravail -= nneed;
+                } else {
+                    const unsigned more = nneed - ravail;
+                    const unsigned take = more > TAIL_CHUNK ? more : TAIL_CHUNK;
+                    const int leader = __ffsll((long long)m) - 1;
+                    unsigned base = 0;
+                    if (lane == leader) base = atomicAdd(q.ctr + 2, take);
+                    base = __shfl(base, leader);
+                    p = r < ravail ? rbase + r : base + (r - ravail);
+                    rbase = base + more;
+                    ravail = take - more;
+                }
+                if (rbase >= n) exhausted = true;
+                if (need && p < n) {
+                    bq_load(q, stride, p, box, cell, s);
+                    cc = make_cc(*boxes[box].kchem, boxes[box].nH[cell], boxes[box].T[cell]);
+                    active = true;
                 }
             }
         }

@@ -494,9 +494,13 @@ __device__ __forceinline__ double chem_finish(const KChem &k, const CC &cc, cons
 
 // Queue of cells still subcycling after the head pass (structure of arrays
 // in caller scratch): the cell index, the attempt counters, and the partial
-// state {N[3], fs[3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}, followed with
-// smoothed RT by {Nr[3], fb[3]}.
+// state {N[3], fs[3], x_HII, x_HeII, x_HeIII, T_mu, rem, h}; the grid's queue
+// adds the inputs of the cell constants {n_H, T at the start of the step}
+// (so that a refill does not wait on a load that depends on the cell
+// index), and with smoothed RT {Nr[3], fb[3]}.
 constexpr int QV = 12;
+constexpr int QV_CC = QV;
+constexpr int QV_GRID = QV + 2;
 
 // a queued cell that took at least this many attempts in the previous pass
 // goes to the tail's first region
@@ -504,7 +508,16 @@ constexpr int QV = 12;
 #define RT_TAIL_LONG_ATTEMPTS 48
 #endif
 constexpr int TAIL_LONG_ATTEMPTS = RT_TAIL_LONG_ATTEMPTS;
-constexpr int QV_SMOOTH = 18;
+constexpr int QV_SMOOTH = QV_GRID + 6;
+
+// queue positions a tail wave reserves at a time (at least the lanes that
+// need a cell): most refills then take no atomic on the shared counter.  One
+// wave's width: the first reservation gives every lane a cell, and a wave
+// never holds a second of the long chains at the queue's front in reserve.
+#ifndef RT_TAIL_CHUNK
+#define RT_TAIL_CHUNK 64
+#endif
+constexpr unsigned TAIL_CHUNK = RT_TAIL_CHUNK;
 
 __device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CS &) {}
 __device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CSR &s)
@@ -513,8 +526,8 @@ __device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, co
     const size_t c = q.stride;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-        v[(size_t)(QV + g) * c] = s.Nr[g];
-        v[(size_t)(QV + 3 + g) * c] = s.fb[g];
+        v[(size_t)(QV_GRID + g) * c] = s.Nr[g];
+        v[(size_t)(QV_GRID + 3 + g) * c] = s.fb[g];
     }
 }
 __device__ __forceinline__ void q_load_rates(const QueueView &q, uint32_t p, CS &) {}
@@ -524,13 +537,13 @@ __device__ __forceinline__ void q_load_rates(const QueueView &q, uint32_t p, CSR
     const size_t c = q.stride;
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-        s.Nr[g] = v[(size_t)(QV + g) * c];
-        s.fb[g] = v[(size_t)(QV + 3 + g) * c];
+        s.Nr[g] = v[(size_t)(QV_GRID + g) * c];
+        s.fb[g] = v[(size_t)(QV_GRID + 3 + g) * c];
     }
 }
 
 template <class S>
-__device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t cell, const S &s)
+__device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t cell, const S &s, const CC &cc)
 {
     q.cell[p] = (int32_t)cell;
     q.acc[p] = s.acc;
@@ -548,11 +561,13 @@ __device__ __forceinline__ void q_store(const QueueView &q, uint32_t p, uint32_t
     v[9 * c] = s.Tmu;
     v[10 * c] = s.rem;
     v[11 * c] = s.h;
+    v[(size_t)QV_CC * c] = cc.nH;
+    v[(size_t)(QV_CC + 1) * c] = cc.Tiso;
     q_store_rates(q, p, s);
 }
 
 template <class S>
-__device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, S &s)
+__device__ __forceinline__ uint32_t q_load(const KChem &k, const QueueView &q, uint32_t p, S &s, CC &cc)
 {
     s.acc = q.acc[p];
     s.att = q.att[p];
@@ -569,6 +584,7 @@ __device__ __forceinline__ uint32_t q_load(const QueueView &q, uint32_t p, S &s)
     s.Tmu = v[9 * c];
     s.rem = v[10 * c];
     s.h = v[11 * c];
+    cc = make_cc(k, v[(size_t)QV_CC * c], v[(size_t)(QV_CC + 1) * c]);
     q_load_rates(q, p, s);
     return (uint32_t)q.cell[p];
 }

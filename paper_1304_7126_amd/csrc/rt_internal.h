@@ -105,7 +105,7 @@ struct QueueView {
     unsigned *cnt[3];   // cells queued per region (each on its own cache line)
     unsigned rbeg[3], rlen[3];  // region offsets and sizes
     int32_t *cell, *acc, *att;
-    double *v;          // QV (smoothed RT: QV_SMOOTH) planes of `stride` doubles
+    double *v;          // QV_GRID (smoothed RT: QV_SMOOTH) planes of `stride` doubles
     unsigned cap;       // cells the head pass may queue
     unsigned stride;    // plane length of the layout
 };

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
     }
     bool queued = false;
     if (p != ~0u) {
-        q_store(q, p, i, s);
+        q_store(q, p, i, s, cc);
         queued = true;
     }
     if (want && !queued) {
@@ -343,6 +343,7 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
     bool raised = false;
+    unsigned rbase = 0, ravail = 0;  // positions this wave has reserved and not yet handed out
     unsigned fl = 0;
     unsigned long long a_acc = 0, a_att = 0, a_max = 0;
     __shared__ unsigned s_hist[64];
@@ -353,20 +354,33 @@ __global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, Chem
             const bool need = !active;
             const unsigned long long m = __ballot(need);
             if (m) {
-                const int leader = __ffsll((long long)m) - 1;
-                unsigned base = 0;
-                if (lane_id() == leader) base = atomicAdd(q.head, (unsigned)__popcll(m));
-                base = __shfl(base, leader);
-                if (base >= n) exhausted = true;
-                if (need) {
-                    const unsigned t = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
-                    if (t < n) {
-                        const unsigned pos = t < n0 ? t : (t < n0 + n1 ? q.rbeg[1] + (t - n0) : q.rbeg[2] + (t - n0 - n1));
-                        cell = q_load(q, pos, s);
-                        cc = make_cc(k, io.nH[cell] * io.ia3, io.T[cell]);
-                        active = true;
-                        first = t < n0;
-                    }
+                const unsigned nneed = (unsigned)__popcll(m);
+                const unsigned r = (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+                unsigned t;
+                if (ravail >= nneed) {
+                    t = rbase + r;
+                    rbase += nneed;
+                    ravail -= nneed;
+                } else {
+                    // what is left of the reservation goes first; a new one
+                    // of at least TAIL_CHUNK positions covers the rest
+                    const unsigned more = nneed - ravail;
+                    const unsigned take = more > TAIL_CHUNK ? more : TAIL_CHUNK;
+                    const int leader = __ffsll((long long)m) - 1;
+                    unsigned base = 0;
+                    if (lane_id() == leader) base = atomicAdd(q.head, take);
+                    base = __shfl(base, leader);
+                    t = r < ravail ? rbase + r : base + (r - ravail);
+                    rbase = base + more;
+                    ravail = take - more;
+                }
+                // positions only grow: past n there is nothing left for this wave
+                if (rbase >= n) exhausted = true;
+                if (need && t < n) {
+                    const unsigned pos = t < n0 ? t : (t < n0 + n1 ? q.rbeg[1] + (t - n0) : q.rbeg[2] + (t - n0 - n1));
+                    cell = q_load(k, q, pos, s, cc);
+                    active = true;
+                    first = t < n0;
                 }
             }
             // a wave holding cells of the first region (the longest chains)
@@ -514,12 +528,13 @@ hipError_t launch_step_fused(int part, bool fp32, int flux, const KGrid &g, cons
 size_t reduction_scratch_bytes() { return (size_t)RED_BLOCKS * sizeof(RedOut); }
 
 // scratch layout: [reduction partials][queue counters, 512 B]
-//                 [cell, acc, att: 3 x cap int32][QV (or QV_SMOOTH) x cap doubles]
+//                 [cell, acc, att: 3 x cap int32][QV_GRID (or QV_SMOOTH) x cap doubles]
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t queue_bytes(unsigned cap, bool smooth)
 {
-    return 512 + align256((size_t)cap * 3 * sizeof(int32_t)) + (size_t)(smooth ? QV_SMOOTH : QV) * cap * sizeof(double);
+    return 512 + align256((size_t)cap * 3 * sizeof(int32_t)) +
+           (size_t)(smooth ? QV_SMOOTH : QV_GRID) * cap * sizeof(double);
 }
 
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
