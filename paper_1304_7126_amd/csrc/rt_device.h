@@ -10,14 +10,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// All device code of the library is compiled without contraction of
-// multiplies and adds into FMAs (explicit fma() calls, as in the math
-// library, are kept): the compiler's choice of which products to fuse can
-// differ between the kernels that inline the same function, and a cell's
-// result must not depend on the kernel that computes it (first pass or
-// queue, grid or batch, step or tape).  The pragma holds to the end of
-// each translation unit that includes this header.
-#pragma clang fp contract(off)
+// Multiplies and adds are fused into FMAs only where they form one source
+// expression (a * b + c): the front end marks exactly those, and the
+// back end fuses every marked one, so the choice does not depend on the
+// kernel that inlines a function.  A cell's result must not depend on the
+// kernel that computes it (first pass or queue, grid or batch, step or
+// tape); fusing across statements, as the compiler's "fast" mode may,
+// could differ between kernels.  The pragma holds to the end of each
+// translation unit that includes this header.
+#pragma clang fp contract(on)
 
 namespace rtm1 {
 
