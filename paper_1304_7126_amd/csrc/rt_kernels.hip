@@ -329,9 +329,11 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
 // Tail pass over the queue: persistent waves whose lanes each take a queued
 // cell, run one attempt per loop trip, and refill from the queue as soon as
 // their cell has filled dt_RT, so that a few slow cells do not hold whole
-// waves of finished lanes.
+// waves of finished lanes.  Compiled for three waves per SIMD: the smoothed
+// variants would otherwise take 176-178 VGPRs and run two (a few bytes of
+// spill at three: 4.6 -> 4.0 ms per tail at 256^3 x 3).
 template <typename R, int M, int V>
-__global__ __launch_bounds__(256) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
+__global__ __launch_bounds__(256, 3) void k_tail(const KChem *__restrict__ kp, ChemIO<R> io, QueueView q, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
     // the regions in order: longest expected chains first
