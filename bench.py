@@ -436,15 +436,18 @@ def main():
     counters_valid = (kernel_source_hash() == COUNTERS_SOURCE_HASH and fp32 and n == 256 and args.flux == "hll"
                       and not args.smooth and floor == 0.0 and not args.no_otsa and args.expansion == 1.0)
     traffic = COUNTERS["read_bytes"] + COUNTERS["write_bytes"] if counters_valid else None
-    # the kernel is bound by its VALU issue rate: counter figures (static,
-    # from the profile) and the live duration
+    # the kernel is bound by its VALU issue rate: counter figures over steps
+    # 101-105 (instruction counts grow with the step as fronts develop),
+    # divided by the duration of those same launches
     alu = None
     if counters_valid:
-        alu = {"valu_issue_frac": COUNTERS["valu_wave_instr"] / (t_head * 1e-3) / VALU_ISSUE_PEAK,
+        t_c = COUNTERS["ms"] * 1e-3
+        alu = {"valu_issue_frac": COUNTERS["valu_wave_instr"] / t_c / VALU_ISSUE_PEAK,
                "lane_util": COUNTERS["lane_util"],
-               "fp64_active_lane_TFLOPs": COUNTERS["fp64_flops_all_lanes"] * COUNTERS["lane_util"] / (t_head * 1e-3) / 1e12,
+               "fp64_active_lane_TFLOPs": COUNTERS["fp64_flops_all_lanes"] * COUNTERS["lane_util"] / t_c / 1e12,
                "fp64_peak_TFLOPs": FP64_VECTOR_PEAK_TFLOPS,
-               "source": "profiles/k_head_fused_256cube_3grp_pmc_valu.md (instruction counts at steps 101-105)"}
+               "steps": "101-105", "ms_per_launch": COUNTERS["ms"],
+               "source": "profiles/k_head_fused_256cube_3grp_pmc_valu.md"}
     roof = {"kernel": "k_head (transport fused with the first chemistry pass)", "bound": "hbm",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic, "traffic_source": "profiles/k_head_fused_256cube_3grp_pmc_bytes.md" if traffic else None,
