@@ -194,10 +194,11 @@ __device__ __forceinline__ void hist_flush(const unsigned *sh, unsigned long lon
 // Cells that finish are written to the destination arrays; the rest go to
 // the queue (or, when it is full, finish in place).
 // Waves per SIMD the head kernel is compiled for: three (168 VGPRs, a few
-// bytes of spill) measured faster than two without spills; the FP64
-// three-group variant spills too much at three and keeps two.
+// bytes of spill) measured faster than two without spills, also for the
+// FP64 three-group variant (191 VGPRs at two waves: 8.7 -> 7.9 ms per head
+// launch at 256^3 x 3 once multiply-adds fuse per expression).
 template <typename R, int M>
-constexpr int head_waves() { return (sizeof(R) == 4 || M < 3) ? 3 : 2; }
+constexpr int head_waves() { return 3; }
 
 // V selects the method variant of the chemistry (V_SMOOTH: it starts from
 // the radiation before injection and transport, io.sm, and takes their
