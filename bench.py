@@ -29,7 +29,7 @@ VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 # 101-105), valid for the kernel sources they were taken with
 # (profiles/k_head_fused_256cube_3grp_pmc_bytes.md and _pmc_valu.md).
 KERNEL_SOURCES = ("rt_kernels.hip", "rt_cell.h", "rt_device.h", "rt_internal.h")
-COUNTERS_SOURCE_HASH = "5a9667547002500f"
+COUNTERS_SOURCE_HASH = "49b77b76363506d5"
 COUNTERS = {"read_bytes": 2534411 * 2 * 1024, "write_bytes": 3102981 * 1024, "valu_wave_instr": 3.1734e+09,
             "lane_util": 0.669, "fp64_flops_all_lanes": 1.173e+11, "ms": 5.595}
 

@@ -196,7 +196,8 @@ __device__ __forceinline__ void hist_flush(const unsigned *sh, unsigned long lon
 // Waves per SIMD the head kernel is compiled for: three (168 VGPRs, a few
 // bytes of spill) measured faster than two without spills, also for the
 // FP64 three-group variant (191 VGPRs at two waves: 8.7 -> 7.9 ms per head
-// launch at 256^3 x 3 once multiply-adds fuse per expression).
+// launch at 256^3 x 3 once multiply-adds fuse per expression) and for the
+// smoothed one (140 bytes of spill at three: 6.9 against 7.5 ms at two).
 template <typename R, int M>
 constexpr int head_waves() { return 3; }
 
@@ -328,9 +329,11 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
 }
 
 // Tail pass over the queue: persistent waves whose lanes each take a queued
-// cell, run one attempt per loop trip, and refill from the queue as soon as
-// their cell has filled dt_RT, so that a few slow cells do not hold whole
-// waves of finished lanes.  Compiled for three waves per SIMD: the smoothed
+// cell, run one attempt per loop trip (an attempt that fails the photon
+// check repeats at once with the halved substep), and refill from the
+// wave's reservation of queue positions as soon as their cell has filled
+// dt_RT, so that a few slow cells do not hold whole waves of finished
+// lanes.  Compiled for three waves per SIMD: the smoothed
 // variants would otherwise take 176-178 VGPRs and run two (a few bytes of
 // spill at three: 4.6 -> 4.0 ms per tail at 256^3 x 3).
 template <typename R, int M, int V>
