@@ -295,7 +295,9 @@ def bench_batch(args):
     """The batching form: 64 periodic boxes (sides 16-96, 1-3 groups, uniform
     densities, 1-8 sources; FP32 transport, FP64 chemistry, GLF), advanced as
     one autotuned batch (one graph launch per step) and, for comparison, one
-    box at a time through rt_step."""
+    box at a time through rt_step, in the same precision and in plain FP64;
+    the batched result is compared with both after the same steps."""
+    import numpy as np
     import torch
 
     import rt_inputs as ri
@@ -315,24 +317,40 @@ def bench_batch(args):
     b.synchronize()
     wall_b = time.perf_counter() - t0
     st = b.stats()
+    fields = ("N", "F", "xHII", "xHeII", "xHeIII", "T")
+    res_b = [{k: b.state_numpy(i)[k] for k in fields} for i in range(len(ws))]
     del b
     torch.cuda.empty_cache()
-    ctxs = []
-    for w, (ijk, nd) in zip(ws, srcs):
-        c = RTContext.for_workload(w, fp32=True)
-        c.load_state(ri.initial_state(w))
-        c.set_sources(ijk, c.source_rates(nd))
-        ctxs.append(c)
-    for _ in range(args.warmup):
+
+    def one_by_one(fp32):
+        ctxs = []
+        for w, (ijk, nd) in zip(ws, srcs):
+            c = RTContext.for_workload(w, fp32=fp32)
+            c.load_state(ri.initial_state(w))
+            c.set_sources(ijk, c.source_rates(nd))
+            ctxs.append(c)
+        for _ in range(args.warmup):
+            for c in ctxs:
+                c.step(dt, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for c in ctxs:
+                c.step(dt, 1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res = [c.state_numpy() for c in ctxs]
         for c in ctxs:
-            c.step(dt, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for c in ctxs:
-            c.step(dt, 1)
-    torch.cuda.synchronize()
-    wall_u = time.perf_counter() - t0
+            c.close()
+        torch.cuda.empty_cache()
+        return wall, res
+
+    wall_u, res_u = one_by_one(True)
+    same = all(np.array_equal(rb[k], ru[k]) for rb, ru in zip(res_b, res_u) for k in fields)
+    wall_64, res_64 = one_by_one(False)
+    # e_inf of the batched (mixed) result against plain FP64, worst box
+    err = {k: max(float(np.max(np.abs(rb[k] - r6[k])) / max(np.max(np.abs(r6[k])), 1e-300))
+                  for rb, r6 in zip(res_b, res_64)) for k in fields}
     out = {"metric": "RT cell-group updates/s, 64 uneven boxes (batching form)",
            "value": cg * args.steps / wall_b, "unit": "cell-group updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall_b * 1e3 / args.steps,
@@ -340,8 +358,12 @@ def bench_batch(args):
            "dtype": "f32 transport / f64 chemistry", "data": "synthetic",
            "config": {"workload": "64 periodic boxes, sides {16..96}, 1-3 groups, GLF", "cells": sum(w.ncell for w in ws),
                       "cell_groups": cg, "tuning": tune["config"]},
-           "one_by_one": {"value": cg * args.steps / wall_u, "ms_per_step": wall_u * 1e3 / args.steps},
+           "one_by_one": {"value": cg * args.steps / wall_u, "ms_per_step": wall_u * 1e3 / args.steps,
+                          "identical_to_batched": same},
            "speedup_vs_one_by_one": wall_u / wall_b,
+           "one_by_one_fp64": {"value": cg * args.steps / wall_64, "ms_per_step": wall_64 * 1e3 / args.steps,
+                               "batched_e_inf_vs_fp64": err},
+           "speedup_vs_one_by_one_fp64": wall_64 / wall_b,
            "chem": {"attempts_per_cell_step": st["attempts_total"] / (sum(w.ncell for w in ws) * args.steps),
                     "flags": st["flags"]}}
     print(json.dumps(out), flush=True)
