@@ -53,6 +53,7 @@ def lib():
         L.or_rate.restype = ctypes.c_int
         L.or_eddington.argtypes = [ctypes.c_double, dp, ctypes.c_double, dp]
         L.or_face_flux.argtypes = [ctypes.POINTER(OrParams), ctypes.c_int, dp, dp, dp]
+        L.or_hll_eig.argtypes = [ctypes.POINTER(OrParams), ctypes.c_int, dp, dp, dp]
         L.or_courant_dt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_courant_dt.restype = ctypes.c_double
         L.or_threads.restype = ctypes.c_int
@@ -339,6 +340,14 @@ class OracleRT:
         out = np.zeros(4)
         lib().or_face_flux(ctypes.byref(self.p), int(d), _dp(UL), _dp(UR), _dp(out))
         return out
+
+    def hll_eig(self, d, U):
+        """(lambda_min, lambda_max) of state U = (N, Fx, Fy, Fz) along axis d
+        from the HLL table (units of c_r), as the HLL flux uses them."""
+        U = np.ascontiguousarray(U, np.float64)
+        lo, hi = np.zeros(1), np.zeros(1)
+        lib().or_hll_eig(ctypes.byref(self.p), int(d), _dp(U), _dp(lo), _dp(hi))
+        return float(lo[0]), float(hi[0])
 
 
 def eddington(N, F, c):

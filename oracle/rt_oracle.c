@@ -349,6 +349,12 @@ static void hll_eig(const or_params *p, int d, const double U[4], double *lmin, 
 #undef TAB
 }
 
+/* The table lookup above, exported for the tests that pin it. */
+void or_hll_eig(const or_params *p, int d, const double U[4], double *lmin, double *lmax)
+{
+    hll_eig(p, d, U, lmin, lmax);
+}
+
 /* Intercell flux at the interface between UL (left) and UR (right) along
  * axis d: eq. (glf) or eq. (hll). */
 void or_face_flux(const or_params *p, int d, const double UL[4], const double UR[4], double Phi[4])

@@ -216,3 +216,55 @@ def test_brute_force_tiny_grids(oracle_mod, bc):
         o.transport(st, dt)
         assert np.allclose(st["N"], Nb, rtol=1e-12, atol=0)
         assert np.allclose(st["F"], Fb, rtol=1e-11, atol=1e-12 * C_R)
+
+
+def test_hll_eigenvalues_interpolate_the_table(oracle_mod):
+    # The HLL wave speeds come from the eigenvalue table of Sec. 3.2, read
+    # bilinearly in (f, theta) on uniform nodes, theta the angle between F
+    # and the +d axis.  A table of the form a + b f + e theta + g f theta is
+    # reproduced exactly at any state; a random table gives back its node
+    # values at the nodes and the mean of the four neighbours midway.
+    nf, nth = 11, 13
+    fs = np.linspace(0.0, 1.0, nf)
+    ths = np.linspace(0.0, np.pi, nth)
+    tab = np.empty((nf, nth, 2))
+    tab[..., 0] = -(0.2 + 0.5 * fs[:, None] + 0.1 * ths[None, :] + 0.03 * fs[:, None] * ths[None, :])
+    tab[..., 1] = 0.3 + 0.4 * fs[:, None] - 0.05 * ths[None, :]
+    o = make((3, 3, 3), (0,) * 6, flux=1, hll=tab)
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        N = rng.uniform(0.1, 2.0)
+        f = rng.uniform(0.0, 1.0)
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        d = int(rng.integers(0, 3))
+        lo, hi = o.hll_eig(d, np.r_[N, f * C_R * N * u])
+        th = np.arccos(u[d])
+        assert lo == pytest.approx(-(0.2 + 0.5 * f + 0.1 * th + 0.03 * f * th), rel=1e-12, abs=1e-14)
+        assert hi == pytest.approx(0.3 + 0.4 * f - 0.05 * th, rel=1e-12, abs=1e-14)
+    # f above 1 reads the f = 1 row; an empty cell with flux is a beam (f = 1)
+    lo, hi = o.hll_eig(0, [1.0, 3.0 * C_R, 0.0, 0.0])
+    assert (lo, hi) == pytest.approx((tab[-1, 0, 0], tab[-1, 0, 1]), rel=1e-12)
+    lo, hi = o.hll_eig(1, [0.0, 0.0, -2.0, 0.0])
+    assert (lo, hi) == pytest.approx((tab[-1, -1, 0], tab[-1, -1, 1]), rel=1e-12)
+    # an empty cell without flux: f = 0, theta = 0
+    assert o.hll_eig(2, [0.0, 0.0, 0.0, 0.0]) == pytest.approx((tab[0, 0, 0], tab[0, 0, 1]), rel=1e-12)
+    tab2 = rng.uniform(-1.0, 1.0, (nf, nth, 2))
+    o2 = make((3, 3, 3), (0,) * 6, flux=1, hll=tab2)
+
+    def state(f, th, d):
+        # unit vector at angle th from axis d, in the plane of axes d and d+1
+        u = np.zeros(3)
+        u[d] = np.cos(th)
+        u[(d + 1) % 3] = np.sin(th)
+        return np.r_[1.0, f * C_R * u]
+    for i in (1, 4, nf - 1):  # at f = 0 there is no flux and theta reads 0
+        for k in (0, 6, nth - 1):
+            d = (i + k) % 3
+            assert o2.hll_eig(d, state(fs[i], ths[k], d)) == pytest.approx(tuple(tab2[i, k]), rel=1e-9, abs=1e-9)
+    for i in (0, 5, nf - 2):
+        for k in (0, 7, nth - 2):
+            d = (i + 2 * k) % 3
+            mid = tab2[i:i + 2, k:k + 2].mean(axis=(0, 1))
+            got = o2.hll_eig(d, state(0.5 * (fs[i] + fs[i + 1]), 0.5 * (ths[k] + ths[k + 1]), d))
+            assert got == pytest.approx(tuple(mid), rel=1e-9, abs=1e-9)
