@@ -299,11 +299,12 @@ void or_eddington(double N, const double F[3], double c, double D[9])
 }
 
 /* Physical flux along axis d of eq. (dUdt): G = [F_d, c^2 P_d.], P = D N.
- * A cell with N <= 0 carries no pressure. */
+ * A cell with N <= 0 carries no pressure, and so does a density so small
+ * that 1/(c_r N) overflows: its reduced flux is not representable. */
 static void flux_G(int d, const double U[4], double c, double G[4])
 {
     G[0] = U[1 + d];
-    if (U[0] <= 0.0) {
+    if (U[0] <= 0.0 || isinf(1.0 / (c * U[0]))) {
         G[1] = G[2] = G[3] = 0.0;
         return;
     }

@@ -268,3 +268,20 @@ def test_hll_eigenvalues_interpolate_the_table(oracle_mod):
             mid = tab2[i:i + 2, k:k + 2].mean(axis=(0, 1))
             got = o2.hll_eig(d, state(0.5 * (fs[i] + fs[i + 1]), 0.5 * (ths[k] + ths[k + 1]), d))
             assert got == pytest.approx(tuple(mid), rel=1e-9, abs=1e-9)
+
+
+def test_vanishing_density_carries_no_pressure(oracle_mod):
+    # reading of Sec. 2 (f <= 1 must hold): N <= 0, and a density so small
+    # that 1/(c_r N) overflows, carry no radiation pressure; the flux
+    # component of G is F_d either way.  With UL = UR the GLF flux is G.
+    o = make((2, 2, 2), (0,) * 6)
+    for N in (0.0, 1e-320, -1e-10):
+        U = np.array([N, 1e-300, -2e-300, 0.0])
+        for d in range(3):
+            G = o.face_flux(d, U, U)
+            assert G[0] == U[1 + d] and G[1] == 0.0 and G[2] == 0.0 and G[3] == 0.0, (N, d, G)
+    # a density just above that limit keeps its pressure: f = 1 along F
+    N = 1e-300 / C_R
+    U = np.array([N, 1e-300, 0.0, 0.0])
+    G = o.face_flux(0, U, U)
+    assert G[1] == pytest.approx(C_R * C_R * N, rel=1e-14) and G[2] == 0.0
