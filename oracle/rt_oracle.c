@@ -350,6 +350,25 @@ static void hll_eig(const or_params *p, int d, const double U[4], double *lmin, 
 #undef TAB
 }
 
+/* Reduced flux component f cos(theta) of a cell along axis d, with f and
+ * theta as the table lookup takes them (f capped at 1; an empty cell with
+ * flux is a beam, f = 1). */
+static double reduced_flux(const or_params *p, int d, const double U[4])
+{
+    double Fn = norm3(U + 1);
+    if (!(Fn > 0.0)) return 0.0;
+    double f;
+    if (U[0] > 0.0)
+        f = Fn / (p->c_r * U[0]);
+    else
+        f = 1.0;
+    if (f > 1.0) f = 1.0;
+    double ct = U[1 + d] / Fn;
+    if (ct > 1.0) ct = 1.0;
+    if (ct < -1.0) ct = -1.0;
+    return f * ct;
+}
+
 /* The table lookup above, exported for the tests that pin it. */
 void or_hll_eig(const or_params *p, int d, const double U[4], double *lmin, double *lmax)
 {
@@ -372,6 +391,17 @@ void or_face_flux(const or_params *p, int d, const double UL[4], const double UR
     double l0m, l0p, l1m, l1p;
     hll_eig(p, d, UL, &l0m, &l0p);
     hll_eig(p, d, UR, &l1m, &l1p);
+    /* The exact eigenvalues of a cell always bracket its reduced flux
+     * f cos(theta) = F_d/(c N) (f capped at 1); the bilinear table does not
+     * (at f = 1 the chord of cos(theta) between nodes misses it by up to
+     * ~1e-4), and a speed range that excludes it lets this flux draw
+     * photons out of an empty cell upstream of a beam.  Each cell's range
+     * is widened to contain it. */
+    double aL = reduced_flux(p, d, UL), aR = reduced_flux(p, d, UR);
+    l0m = fmin(l0m, aL);
+    l0p = fmax(l0p, aL);
+    l1m = fmin(l1m, aR);
+    l1p = fmax(l1p, aR);
     double lp = fmax(0.0, fmax(l0p, l1p)) * c;
     double lm = fmin(0.0, fmin(l0m, l1m)) * c;
     if (lp - lm == 0.0) {
@@ -433,9 +463,14 @@ static void neighbour_U(const or_params *p, const double *N, const double *F, in
  * not say how unrealisable states are treated; left alone, an exact beam
  * entering through a face grows an instability under HLL, whose wave speeds
  * at f = 1 are both +c while the closure capped at f = 1 propagates a
- * backward wave.  N <= 0 is left as it is. */
+ * backward wave.  A negative photon density (with the widened speeds of
+ * or_face_flux only rounding leaves one, next to a beam) empties the cell. */
 static void limit_flux(double U[4], double c)
 {
+    if (U[0] < 0.0) {
+        U[0] = U[1] = U[2] = U[3] = 0.0;
+        return;
+    }
     /* as in the closure, a density so small that 1/(c_r N) overflows counts as empty */
     double icn = 1.0 / (c * U[0]);
     if (!(U[0] > 0.0) || isinf(icn)) return;

@@ -285,3 +285,59 @@ def test_vanishing_density_carries_no_pressure(oracle_mod):
     U = np.array([N, 1e-300, 0.0, 0.0])
     G = o.face_flux(0, U, U)
     assert G[1] == pytest.approx(C_R * C_R * N, rel=1e-14) and G[2] == 0.0
+
+
+def test_hll_speeds_contain_the_reduced_flux(oracle_mod):
+    # The exact eigenvalues of the flux Jacobian bracket a cell's reduced
+    # flux f cos(theta) (checked here by an eigen-solve); the HLL flux keeps
+    # that bracket with the widened table speeds, so an empty cell upstream
+    # of a beam gives nothing to it: Phi_N(empty | beam) <= 0.
+    rng = np.random.default_rng(5)
+    fs = np.concatenate([np.ones(200), rng.uniform(0.9, 1.0, 200), rng.uniform(0, 0.9, 100)])
+    ths = rng.uniform(0, np.pi / 2, fs.size)
+    o = make((2, 2, 2), (0,) * 6, flux=1, hll=physics.hll_table())
+    empty = np.zeros(4)
+    for f, th in zip(fs, ths):
+        if f < 1:
+            ev = np.linalg.eigvals(physics.m1_jacobian(f, np.array([th]))[0]).real
+            assert ev.min() <= f * math.cos(th) <= ev.max()
+        ph = rng.uniform(0, 2 * np.pi)
+        n = np.array([math.cos(th), math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph)])
+        R = np.array([1.0, *(f * C_R * n)])
+        lo, hi = o.hll_eig(0, R)
+        phi = o.face_flux(0, empty, R)
+        assert phi[0] <= 1e-15 * C_R, (f, th, lo, hi, f * math.cos(th), phi[0])
+
+
+def test_hll_beam_next_to_empty_cells_stays_positive_and_conservative(oracle_mod):
+    # a beam at an angle between the table's nodes in an otherwise empty box:
+    # no cell goes negative and no photon is created
+    for th in (0.3, 1.0, 2.2):
+        o = make((5, 5, 5), (1,) * 6, flux=1, hll=physics.hll_table())
+        st = random_state((5, 5, 5), 1, np.random.default_rng(0))
+        st["N"][:] = 0.0
+        st["F"][:] = 0.0
+        st["N"][0, 2, 2, 2] = 1.0
+        st["F"][0, :, 2, 2, 2] = C_R * np.array([math.cos(th), math.sin(th), 0.0])
+        o.transport(st, o.courant_dt())
+        assert st["N"].min() >= 0.0
+        assert abs(st["N"].sum() - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("flux", [0, 1])
+def test_transport_keeps_photon_density_nonnegative(oracle_mod, flux):
+    # random states with empty cells and exact beams at random angles,
+    # periodic, several steps: N >= 0 everywhere and the total conserved
+    rng = np.random.default_rng(7)
+    n = (7, 6, 5)
+    o = make(n, (0,) * 6, flux=flux, hll=physics.hll_table(), M=1)
+    st = random_state(n, 1, rng)
+    st["N"][rng.uniform(size=st["N"].shape) < 0.5] = 0.0
+    st["N"] *= 10.0 ** rng.uniform(-6, 0, st["N"].shape)
+    d = st["F"] / np.maximum(np.linalg.norm(st["F"], axis=1, keepdims=True), 1e-300)
+    st["F"] = np.ascontiguousarray(d * C_R * st["N"][:, None])  # every cell a beam
+    tot = st["N"].sum()
+    for _ in range(6):
+        o.transport(st, o.courant_dt())
+        assert st["N"].min() >= 0.0
+    assert abs(st["N"].sum() / tot - 1) < 1e-13
