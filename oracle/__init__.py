@@ -57,6 +57,8 @@ def lib():
         L.or_courant_dt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_courant_dt.restype = ctypes.c_double
         L.or_threads.restype = ctypes.c_int
+        L.or_diagnostics.argtypes = [ctypes.POINTER(OrParams), dp, dp, dp, dp, dp]
+        L.or_boundary_outflow.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp]
         lp = ctypes.POINTER(ctypes.c_longlong)
         L.or_step_cells.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp, dp, dp, dp, dp,
                                     ctypes.c_int, lp, dp, dp, dp, dp, ip, ip]
@@ -292,6 +294,63 @@ class OracleRT:
         Fr = (st["F"] - F0) / dt
         st["N"], st["F"] = N0, F0
         return self.thermochem_rates(st, dt, Nr, Fr, want_counts=want_counts)
+
+    # -- diagnostics (the photon budget of the operator split) -------------
+    def diagnostics(self, st):
+        """Photons per group (sum N dx^3), ionised hydrogen (sum x_HII n_H
+        dx^3), the largest reduced flux |F|/(c_r N) over cells with N > 0 and
+        the smallest photon density of a state."""
+        out = np.zeros(6)
+        c64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        arrs = [c64(st[k]) for k in ("N", "F", "xHII", "nH")]
+        lib().or_diagnostics(ctypes.byref(self.p), *[_dp(a) for a in arrs], _dp(out))
+        return {"photons": out[:3].copy(), "ionised_H": float(out[3]), "max_f": float(out[4]),
+                "min_N": float(out[5])}
+
+    def boundary_outflow(self, st, dt):
+        """Photons per group one transport step of dt carries out through the
+        boundary faces (the N face flux against each face's ghost cell times
+        dx^2 dt, positive outwards), from the state it starts from."""
+        out = np.zeros(3)
+        c64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        N, F = c64(st["N"]), c64(st["F"])
+        lib().or_boundary_outflow(ctypes.byref(self.p), float(dt), _dp(N), _dp(F), _dp(out))
+        return out
+
+    def step_ledger(self, st, dt, ijk=None, ndot=None, ledger=None):
+        """One plain operator-split step (injection, transport,
+        thermochemistry) that also books its photon ledger: photons injected
+        (sum of rate x dt), carried out through the boundary faces by the
+        transport, absorbed by the chemistry (photons entering minus leaving
+        it), the histogram of accepted substeps per cell (bin 63: 63 or
+        more), substep and attempt totals, the largest attempt count and the
+        chemistry flags.  Accumulates into `ledger` (a dict from an earlier
+        call, or None to start one) and returns it with the diagnostics of
+        the new state."""
+        if ledger is None:
+            z3 = np.zeros(3)
+            ledger = {"injected": z3.copy(), "outflow": z3.copy(), "absorbed": z3.copy(),
+                      "substep_hist": np.zeros(64, np.int64), "substeps_total": 0, "attempts_total": 0,
+                      "attempts_max": 0, "flags": 0}
+        V = self.dx ** 3
+        if ijk is not None and len(ijk):
+            nd = np.asarray(ndot, np.float64).reshape(len(ijk), self.M)
+            ledger["injected"][: self.M] += nd.sum(axis=0) * dt
+            self.inject(st, dt, ijk, ndot)
+        ledger["outflow"] += self.boundary_outflow(st, dt)
+        self.transport(st, dt)
+        before = st["N"].reshape(self.M, -1).sum(axis=1) * V
+        flags, nacc, natt = self.thermochem(st, dt, want_counts=True)
+        after = st["N"].reshape(self.M, -1).sum(axis=1) * V
+        ledger["absorbed"][: self.M] += before - after
+        ledger["substep_hist"] += np.bincount(np.minimum(nacc.ravel(), 63), minlength=64)
+        ledger["substeps_total"] += int(nacc.sum())
+        ledger["attempts_total"] += int(natt.sum())
+        ledger["attempts_max"] = max(ledger["attempts_max"], int(natt.max()))
+        ledger["flags"] |= int(flags)
+        ledger["nacc"], ledger["natt"] = nacc, natt
+        ledger.update(self.diagnostics(st))
+        return ledger
 
     def step_cells(self, st, dt, cells, N_pre=None):
         """Transport + thermochemistry of the listed cells (linear indices)

@@ -959,3 +959,81 @@ int or_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================
+ * Diagnostics of a step (the photon budget of the operator split, Sec. 3):
+ * photons per group, ionised hydrogen, largest reduced flux, smallest
+ * photon density, and the photons carried through the boundary faces.
+ * ====================================================================== */
+
+/* out[0..2]: sum over cells of N_g dx^3 (groups >= M: 0); out[3]: sum of
+ * x_HII n_H dx^3; out[4]: max over cells and groups with N > 0 of
+ * |F|/(c_r N); out[5]: min over cells and groups of N.  Plain loops in
+ * cell order. */
+void or_diagnostics(const or_params *p, const double *N, const double *F, const double *xHII,
+                    const double *nH, double *out)
+{
+    size_t nc = (size_t)p->nx * p->ny * p->nz;
+    double V = p->dx * p->dx * p->dx;
+    double ph[3] = {0.0, 0.0, 0.0}, ion = 0.0, maxf = 0.0, minN = INFINITY;
+    for (int g = 0; g < p->M; g++) {
+        for (size_t i = 0; i < nc; i++) {
+            double n = N[(size_t)g * nc + i];
+            double Fv[3];
+            for (int d = 0; d < 3; d++) Fv[d] = F[(size_t)(3 * g + d) * nc + i];
+            ph[g] += n;
+            if (n < minN) minN = n;
+            if (n > 0.0) {
+                double f = norm3(Fv) / (p->c_r * n);
+                if (f > maxf) maxf = f;
+            }
+        }
+    }
+    for (size_t i = 0; i < nc; i++) ion += xHII[i] * nH[i];
+    for (int g = 0; g < 3; g++) out[g] = ph[g] * V;
+    out[3] = ion * V;
+    out[4] = maxf;
+    out[5] = minN;
+}
+
+/* Photons that one transport step of length dt carries out of the grid
+ * through its boundary (non-periodic) faces, per group: the N component
+ * of the face flux (eq. glf or hll, against the ghost cell of the face's
+ * boundary condition) times the face area dx^2 and dt, counted positive
+ * outwards (an inflow face counts its entering beam negative).  out[g],
+ * groups >= M: 0.  N, F: the state the transport starts from. */
+void or_boundary_outflow(const or_params *p, double dt, const double *N, const double *F, double *out)
+{
+    int n[3] = {p->nx, p->ny, p->nz};
+    size_t nc = (size_t)p->nx * p->ny * p->nz;
+    for (int g = 0; g < 3; g++) out[g] = 0.0;
+    for (int g = 0; g < p->M; g++) {
+        double sum = 0.0;
+        for (int d = 0; d < 3; d++) {
+            for (int side = 0; side < 2; side++) {
+                if (p->bc[2 * d + side] == OR_BC_PERIODIC) continue;
+                int c[3];
+                /* every cell of the face layer */
+                int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
+                for (int j2 = 0; j2 < n[a2]; j2++)
+                    for (int j1 = 0; j1 < n[a1]; j1++) {
+                        c[d] = side ? n[d] - 1 : 0;
+                        c[a1] = j1;
+                        c[a2] = j2;
+                        size_t i = (size_t)c[0] + (size_t)p->nx * ((size_t)c[1] + (size_t)p->ny * c[2]);
+                        double UC[4], UG[4], Phi[4];
+                        load_U(N, F, nc, g, i, UC);
+                        neighbour_U(p, N, F, g, c[0], c[1], c[2], d, side ? +1 : -1, UG);
+                        if (side) {
+                            or_face_flux(p, d, UC, UG, Phi);
+                            sum += Phi[0];
+                        } else {
+                            or_face_flux(p, d, UG, UC, Phi);
+                            sum -= Phi[0];
+                        }
+                    }
+            }
+        }
+        out[g] = sum * dt * p->dx * p->dx;
+    }
+}
