@@ -78,10 +78,16 @@ __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6])
 // After an HLL update a flux above c N is scaled back to c N: at f > 1 the
 // capped closure propagates a backward wave that the table's speeds (both
 // +c at f = 1) do not resolve, and an exact beam next to its source face
-// would grow it from rounding.  Empty (and vanishing) densities are left.
+// would grow it from rounding.  A negative density (with speeds that
+// contain each cell's reduced flux only rounding leaves one, next to a
+// beam) empties the cell; vanishing densities are left.
 template <typename R>
-__device__ __forceinline__ void limit_flux(R N, R &Fx, R &Fy, R &Fz, R c)
+__device__ __forceinline__ void limit_flux(R &N, R &Fx, R &Fy, R &Fz, R c)
 {
+    if (N < R(0)) {
+        N = Fx = Fy = Fz = R(0);
+        return;
+    }
     const R icN = rcp(c * N);
     if (!(N > R(0)) || isinf(icN)) return;
     const R ax = Fx * icN, ay = Fy * icN, az = Fz * icN;
@@ -106,7 +112,12 @@ __device__ __forceinline__ void prow(const R P[6], int d, R &px, R &py, R &pz)
 // ---------------------------------------------------------------------
 // HLL wave speeds of a cell along axis d (units of c): bilinear in the
 // table of (lambda_min, lambda_max) over f in [0,1] (nf nodes) and the flux
-// angle theta in [0,pi] (nth nodes), theta = acos(F_d/|F|).
+// angle theta in [0,pi] (nth nodes), theta = acos(F_d/|F|), widened to
+// contain the cell's reduced flux f cos(theta).  The exact eigenvalues
+// always contain it; the interpolated ones need not (at f = 1 the chord of
+// cos(theta) between two nodes misses it by up to ~1e-4), and a range that
+// excludes it lets the flux draw photons out of an empty cell upstream of
+// a beam.
 // ---------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, int nth, R N, R Fx, R Fy,
@@ -147,6 +158,9 @@ __device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, in
     const R a00 = (R(1) - wf) * (R(1) - wt), a10 = wf * (R(1) - wt), a01 = (R(1) - wf) * wt, a11 = wf * wt;
     lmin = a00 * t00[0] + a10 * t10[0] + a01 * t01[0] + a11 * t11[0];
     lmax = a00 * t00[1] + a10 * t10[1] + a01 * t01[1] + a11 * t11[1];
+    const R a = f * ct;
+    lmin = lmin < a ? lmin : a;
+    lmax = lmax > a ? lmax : a;
 }
 
 // ---------------------------------------------------------------------

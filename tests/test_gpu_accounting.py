@@ -8,7 +8,10 @@ boundary faces, and the histogram of accepted substeps.
   - one step against the oracle: absorbed = sum over cells of the photons
     entering minus leaving the chemistry, outflow = photons lost by the
     transport, histogram = the oracle's accepted-substep counts;
-  - the fused step, the split calls and repeated runs give identical sums.
+  - the fused step, the split calls and repeated runs give identical sums;
+  - every field of rt_get_stats against the oracle's step ledger over
+    several steps (photons, ionised hydrogen, largest reduced flux, smallest
+    density, injected, absorbed, outflow, substep histogram and totals).
 """
 import numpy as np
 import pytest
@@ -124,3 +127,46 @@ def test_chemistry_alone_is_accounted_and_off_means_zero():
     s = ctx.stats()
     assert abs(s["absorbed"][0] - (p0 - s["photons"][0])) <= 1e-13 * p0
     assert sum(s["substep_hist"]) == np.prod(n)
+
+
+@pytest.mark.parametrize("bc,flux,fp32", [(BCS[2], 1, False), (BCS[1], 0, False), (BCS[0], 1, False),
+                                          (BCS[2], 1, True)])
+def test_stats_match_oracle_ledger(bc, flux, fp32):
+    n = (19, 17, 13)
+    ctx, o, st, ijk, nd = loaded(n, bc, 3, flux, fp32=fp32, seed=21)
+    if fp32:
+        # the oracle starts from the values the FP32 state holds
+        st["N"] = st["N"].astype(np.float32).astype(np.float64)
+        st["F"] = st["F"].astype(np.float32).astype(np.float64)
+        ctx.load_state(st)
+    ctx.set_accounting(True)
+    ctx.reset_stats()
+    dt = ctx.courant_dt()
+    steps = 4
+    led = None
+    for _ in range(steps):
+        ctx.step(dt, 1)
+        led = o.step_ledger(st, dt, ijk, o.source_rates(nd), led)
+    s = ctx.stats()
+    g = ctx.state_numpy()
+    print(f"# stats vs ledger bc={bc} flux={flux} fp32={fp32}", flush=True)
+    if not fp32:
+        # trace-matched run: per-cell counters first, then every integer exactly
+        assert np.array_equal(g["nacc"], led["nacc"]) and np.array_equal(g["natt"], led["natt"])
+        assert np.array_equal(np.array(s["substep_hist"]), led["substep_hist"])
+        assert s["substeps_total"] == led["substeps_total"]
+        assert s["attempts_total"] == led["attempts_total"]
+        assert s["attempts_max"] == led["attempts_max"]
+    assert s["flags"] == led["flags"] == 0
+    tol = 1e-5 if fp32 else 1e-12
+    tot = np.array(led["photons"]) + led["injected"]
+    for k in ("photons", "injected"):
+        assert np.allclose(s[k], led[k], rtol=tol, atol=0), (k, s[k], led[k])
+    for k in ("absorbed", "outflow"):
+        # differences of photon totals: bounded relative to the totals
+        assert np.all(np.abs(np.array(s[k]) - led[k]) <= tol * np.abs(led[k]) + 10 * tol * tot), (k, s[k], led[k])
+    assert s["ionised_H"] == pytest.approx(led["ionised_H"], rel=tol)
+    assert s["max_f"] == pytest.approx(led["max_f"], rel=tol)
+    assert s["min_N"] == pytest.approx(led["min_N"], rel=tol, abs=0)
+    if bc != BCS[0]:
+        assert np.all(np.abs(led["outflow"]) > 0)

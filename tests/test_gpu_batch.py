@@ -135,3 +135,50 @@ def test_autotuner_picks_a_config_and_keeps_state(tmp_path, monkeypatch):
         g1, g2 = b.state_numpy(i), ref.state_numpy(i)
         for k in FIELDS:
             assert np.array_equal(g1[k], g2[k]), (i, k)
+
+
+def test_batching_workload_subset_mixed_matches_oracle():
+    # the 64-box batching workload in its own precision (FP32 transport, FP64
+    # chemistry): one box of each side 16, 24, 32, 48, 64, 96 is checked
+    # against the oracle on sampled cells at step 100 (oracle steps from the
+    # batch's pre-step state), the two smallest over their whole 100 steps
+    from test_gpu_fullsize import FP32_DARK, FP32_EPS, FP32_FLOOR, compare_sampled, perturbed_oracle, sample_cells
+    specs = ri.batch_boxes(64, seed=0)
+    b, ws, srcs = make_batch(specs, True)
+    dt = b.courant_dt()
+    pick = {}
+    for i, s in enumerate(specs):
+        pick.setdefault(s.side, i)
+    assert sorted(pick) == [16, 24, 32, 48, 64, 96]
+    steps = 100
+    b.step(dt, steps - 1)
+    pre = {i: b.state_numpy(i) for i in pick.values()}
+    b.step(dt, 1)
+    for side, i in sorted(pick.items()):
+        w = ws[i]
+        print(f"# batch box {i}: side {side}, M = {w.spectrum.M}, n_H {w.nH_mean:.3g}", flush=True)
+        g = b.state_numpy(i)
+        st = dict(pre[i])
+        o = oracle.OracleRT.for_workload(w)
+        ijk, nd = srcs[i]
+        o.inject(st, dt, ijk, o.source_rates(nd))
+        cells = sample_cells(w, ijk, st["natt"].ravel(), 1024, i)
+        r = o.step_cells(st, dt, cells)
+        # dense boxes amplify the FP32 rounding of the transport: the limits
+        # include 10x the oracle's own response to a perturbation of that
+        # size; cells behind the fronts hold densities below FP32's range
+        compare_sampled(w, st, g, cells, r, 1e-5, spread=perturbed_oracle(o, st, dt, cells, FP32_EPS),
+                        dark=FP32_DARK, abs_floor=FP32_FLOOR)
+    for side in (16, 24):
+        i = pick[side]
+        w = ws[i]
+        o = oracle.OracleRT.for_workload(w)
+        st = ri.initial_state(w)
+        ijk, nd = srcs[i]
+        ondot = o.source_rates(nd)
+        for _ in range(steps):
+            o.step(st, dt, ijk, ondot)
+        g = b.state_numpy(i)
+        # FP32 rounding of N, F once per step, carried through the chemistry
+        for k in ("xHII", "xHeII", "xHeIII", "T", "N", "F"):
+            assert rel_err(g[k], st[k]) < 1e-5, (side, k, rel_err(g[k], st[k]))
