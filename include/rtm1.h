@@ -246,10 +246,23 @@ rt_status rt_transport(rt_ctx *ctx, double dt);
 rt_status rt_thermochem(rt_ctx *ctx, double dt);
 
 /* nsteps full steps: injection, transport, thermochemistry (Sec. 3).
- * Transport and thermochemistry run fused in one pass over the grid; the
- * result equals rt_inject, rt_transport, rt_thermochem in sequence.
+ * The result equals rt_inject, rt_transport, rt_thermochem in sequence,
+ * bit for bit, whichever transport kernel runs (rt_set_transport_path).
  * dt <= 0 uses the Courant step with factor 0.8. */
 rt_status rt_step(rt_ctx *ctx, double dt, int nsteps);
+
+/* Kernel arrangement of the transport (Sec. 3.2); results are the same bits
+ * on every path:
+ *   RT_PATH_AUTO    the z-marching kernel where it fits, else per cell
+ *   RT_PATH_CELL    one thread per cell evaluates its whole 7-point stencil;
+ *                   rt_step fuses it with the first chemistry pass
+ *   RT_PATH_ZMARCH  workgroups march x-row tiles through z, evaluating each
+ *                   cell's closure and wave speeds once and passing them to
+ *                   the faces through LDS and registers; rt_step runs it,
+ *                   then the chemistry passes.  Needs nx <= 1024 (FP32
+ *                   transport) or nx <= 512 (FP64): RT_EINVAL otherwise. */
+enum { RT_PATH_AUTO = 0, RT_PATH_CELL = 1, RT_PATH_ZMARCH = 2 };
+rt_status rt_set_transport_path(rt_ctx *ctx, int path);
 
 /* Launch tuning (results do not depend on it): head_attempts = chemistry
  * attempts per cell in the first pass before a cell is queued for the

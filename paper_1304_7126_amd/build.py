@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtm1.so")
-SOURCES = ["rt_api.hip", "rt_kernels.hip", "rt_batch.hip", "rt_adjoint.hip"]
+SOURCES = ["rt_api.hip", "rt_kernels.hip", "rt_transport.hip", "rt_batch.hip", "rt_adjoint.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -48,6 +48,10 @@ struct rt_ctx {
     unsigned qcap = 0;               // chemistry queue capacity (cells)
     unsigned qcap_max = 0;           // capacity the scratch size is computed for
     int head_attempts = HEAD_ATTEMPTS;
+    // kernel arrangement of the transport (rt_set_transport_path) and the
+    // transport blocks whose accounting partials the step's ledger sums
+    int path = RT_PATH_AUTO;
+    unsigned acct_nblk = 0;
     // photon accounting
     bool acct = false;
     bool acct_pending = false;       // transport partials of the current step
@@ -445,10 +449,18 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
 // per-cell attempt counts of the previous chemistry pass (one byte per cell)
 static size_t prev_att_bytes(const rt_ctx *c) { return (c->grid.ncell + 255) & ~(size_t)255; }
 
+// accounting partials: 6 doubles per block of either transport kernel
+static size_t acct_region(const rt_ctx *c)
+{
+    const size_t zb = (size_t)transport_z_blocks(c->fp32, c->grid, c->groups.M) * 6 * sizeof(double);
+    const size_t cb = acct_bytes(c->grid.ncell);
+    return ((zb > cb ? zb : cb) + 255) & ~(size_t)255;
+}
+
 static size_t scratch_need(const rt_ctx *c)
 {
     return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max, c->params.smooth != 0) +
-           acct_bytes(c->grid.ncell) + prev_att_bytes(c);
+           acct_region(c) + prev_att_bytes(c);
 }
 
 // accounting partials: after the reduction partials and the queue
@@ -459,7 +471,13 @@ static double *acct_part(const rt_ctx *c)
 }
 
 // previous-pass attempt counts: after the accounting partials
-static uint8_t *prev_att(const rt_ctx *c) { return (uint8_t *)acct_part(c) + acct_bytes(c->grid.ncell); }
+static uint8_t *prev_att(const rt_ctx *c) { return (uint8_t *)acct_part(c) + acct_region(c); }
+
+// whether the transport runs as the z-marching kernel (else per cell)
+static bool use_zmarch(const rt_ctx *c)
+{
+    return c->path != RT_PATH_CELL && transport_z_fits(c->fp32, c->grid);
+}
 
 extern "C" size_t rt_scratch_bytes(const rt_ctx *c)
 {
@@ -647,14 +665,21 @@ static rt_status do_transport(rt_ctx *c, double dt)
     if (c->params.smooth && c->sm_phase == 2)
         RT_FAIL(c, RT_ESTATE, "smoothed RT: the step's transport has run; its thermochemistry comes next");
     const int s = c->cur, d = 1 - c->cur;
+    const bool zm = use_zmarch(c);
     rt_status r = timed(c, TM_TRANSPORT, [&]() -> rt_status {
         // super-comoving variables: light speed a c_r over dt / a^2 (Sec. 5.4)
         const double a = c->a_cosmo;
-        RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, a * c->groups.c_r, dt / (a * a), c->st.N[s],
-                                   c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth,
-                                   c->acct ? acct_part(c) : nullptr, c->stream));
+        if (zm)
+            RT_HIP(c, launch_transport_z(c->fp32, c->params.flux, c->grid, c->groups.M, a * c->groups.c_r, dt / (a * a),
+                                         c->st.N[s], c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth,
+                                         c->acct ? acct_part(c) : nullptr, c->stream));
+        else
+            RT_HIP(c, launch_transport(c->fp32, c->params.flux, c->grid, c->groups.M, a * c->groups.c_r, dt / (a * a),
+                                       c->st.N[s], c->st.F[s], c->st.N[d], c->st.F[d], c->hll_dev, c->nf, c->nth,
+                                       c->acct ? acct_part(c) : nullptr, c->stream));
         return RT_OK;
     });
+    c->acct_nblk = zm ? transport_z_blocks(c->fp32, c->grid, c->groups.M) : acct_blocks(c->grid.ncell);
     if (r != RT_OK) return r;
     c->cur = d;
     c->acct_pending = c->acct;
@@ -680,7 +705,7 @@ static rt_status acct_close(rt_ctx *c, double dt)
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
     rt_status r = acct_reduce(c);
     if (r != RT_OK) return r;
-    RT_HIP(c, launch_ledger(c->acct_pending ? 2 : 1, acct_part(c), acct_blocks(c->grid.ncell), c->groups.M, V,
+    RT_HIP(c, launch_ledger(c->acct_pending ? 2 : 1, acct_part(c), c->acct_nblk, c->groups.M, V,
                             dt / (c->a_cosmo * c->a_cosmo) * c->grid.dx * c->grid.dx, c->dred, c->dstats, c->stream));
     c->acct_pending = false;
     return RT_OK;
@@ -756,6 +781,7 @@ static rt_status do_fused(rt_ctx *c, double dt)
     c->cur = d;
     if (!c->acct) return RT_OK;
     c->acct_pending = true;
+    c->acct_nblk = acct_blocks(c->grid.ncell);
     return acct_close(c, dt);
 }
 
@@ -790,10 +816,27 @@ extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
     if (!(dt > 0)) dt = 0.8 * dt_limit(c);
     rt_status r = check_ready(c, dt);
     if (r != RT_OK) return r;
+    const bool zm = use_zmarch(c);
     for (int k = 0; k < nsteps; ++k) {
         if ((r = do_inject(c, dt)) != RT_OK) return r;
-        if ((r = do_fused(c, dt)) != RT_OK) return r;
+        if (zm) {
+            // the z-marching transport, then the chemistry passes
+            if ((r = do_transport(c, dt)) != RT_OK) return r;
+            if ((r = do_chem(c, dt)) != RT_OK) return r;
+        } else {
+            if ((r = do_fused(c, dt)) != RT_OK) return r;
+        }
     }
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_transport_path(rt_ctx *c, int path)
+{
+    if (!c) return RT_EINVAL;
+    if (path < RT_PATH_AUTO || path > RT_PATH_ZMARCH) RT_FAIL(c, RT_EINVAL, "path must be RT_PATH_AUTO, _CELL or _ZMARCH");
+    if (path == RT_PATH_ZMARCH && !transport_z_fits(c->fp32, c->grid))
+        RT_FAIL(c, RT_EINVAL, "the z-marching transport needs nx <= %d", c->fp32 ? 1024 : 512);
+    c->path = path;
     return RT_OK;
 }
 

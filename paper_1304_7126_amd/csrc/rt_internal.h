@@ -88,6 +88,17 @@ hipError_t launch_transport(bool fp32, int flux, const KGrid &g, int M, double c
                             const void *Nin, const void *Fin, void *Nout, void *Fout, const void *hll,
                             int nf, int nth, double *acct, hipStream_t s);
 
+// The z-marching transport (rt_transport.hip): same results as
+// launch_transport, for grids whose x-rows fit one workgroup (nx <= 1024 in
+// FP32, 512 in FP64; transport_z_fits).  acct: per workgroup, the sum of the
+// new N and of the outward boundary flux of its group, at 6 b + g and
+// 6 b + 3 + g for b < transport_z_blocks().
+bool transport_z_fits(bool fp32, const KGrid &g);
+unsigned transport_z_blocks(bool fp32, const KGrid &g, int M);
+hipError_t launch_transport_z(bool fp32, int flux, const KGrid &g, int M, double c, double dt, const void *Nin,
+                              const void *Fin, void *Nout, void *Fout, const void *hll, int nf, int nth, double *acct,
+                              hipStream_t s);
+
 // mode 0: record the current photon totals as the pre-chemistry totals;
 // mode 1: absorbed += pre-chemistry totals - current totals;
 // mode 2: as 1 with the pre-chemistry totals and the outflow taken from the

@@ -177,6 +177,12 @@ class RTContext:
         """Launch tuning of the chemistry passes (results do not depend on it)."""
         check(lib().rt_set_tuning(self._h, int(head_attempts), int(queue_cap)), self._h)
 
+    PATHS = {"auto": 0, "cell": 1, "zmarch": 2}
+
+    def set_transport_path(self, path):
+        """Transport kernel arrangement: 'auto', 'cell' or 'zmarch' (same results)."""
+        check(lib().rt_set_transport_path(self._h, self.PATHS[path]), self._h)
+
     def courant_dt(self, courant=0.8):
         v = ctypes.c_double()
         check(lib().rt_courant_dt(self._h, float(courant), ctypes.byref(v)), self._h)
