@@ -182,9 +182,9 @@ __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_
         m1_pressure(Rt.n, Rt.fx, Rt.fy, Rt.fz, c, PR);
         R lLm = 0, lLp = 0, lCm = 0, lCp = 0, lRm = 0, lRp = 0;
         if (FLUX == 1) {
-            hll_speeds(tab, nf, nth, L.n, L.fx, L.fy, L.fz, comp(L, d), c, lLm, lLp);
-            hll_speeds(tab, nf, nth, C.n, C.fx, C.fy, C.fz, comp(C, d), c, lCm, lCp);
-            hll_speeds(tab, nf, nth, Rt.n, Rt.fx, Rt.fy, Rt.fz, comp(Rt, d), c, lRm, lRp);
+            hll_speeds(tab, nf, nth, L.n, L.fx, L.fy, L.fz, d, c, lLm, lLp);
+            hll_speeds(tab, nf, nth, C.n, C.fx, C.fy, C.fz, d, c, lCm, lCp);
+            hll_speeds(tab, nf, nth, Rt.n, Rt.fx, Rt.fy, Rt.fz, d, c, lRm, lRp);
         }
         face_flux<R, FLUX>(L, PL, lLm, lLp, C, PC, lCm, lCp, d, c, Pm);
         face_flux<R, FLUX>(C, PC, lCm, lCp, Rt, PR, lRm, lRp, d, c, Pp);

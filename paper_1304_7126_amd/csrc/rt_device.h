@@ -119,48 +119,86 @@ __device__ __forceinline__ void prow(const R P[6], int d, R &px, R &py, R &pz)
 // excludes it lets the flux draw photons out of an empty cell upstream of
 // a beam.
 // ---------------------------------------------------------------------
+// The part of the lookup shared by the three axes: the table row (f) and,
+// per axis, ct_d = num_d * q (or 1 where the cell has no flux direction).
 template <typename R>
-__device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, int nth, R N, R Fx, R Fy,
-                                           R Fz, R Fd, R c, R &lmin, R &lmax)
+struct HllPrep {
+    R num[3];
+    R q;
+    bool dir;  // false: isotropic (ct = 1)
+    R f;
+    int i;
+    R wf;
+};
+
+template <typename R>
+__device__ __forceinline__ HllPrep<R> hll_prep(int nf, R N, R Fx, R Fy, R Fz, R c)
 {
-    R f, ct;
+    HllPrep<R> p;
     const R icN = rcp(c * N);
     if (N > R(0) && !isinf(icN)) {
         const R ax = Fx * icN, ay = Fy * icN, az = Fz * icN;
         const R an = sqrt(ax * ax + ay * ay + az * az);
-        f = an > R(1) ? R(1) : an;
-        ct = an > R(0) ? (Fd * icN) * rcp(an) : R(1);
+        p.f = an > R(1) ? R(1) : an;
+        p.dir = an > R(0);
+        p.num[0] = ax;
+        p.num[1] = ay;
+        p.num[2] = az;
+        p.q = p.dir ? rcp(an) : R(1);
     } else {
         // empty cell: a beam if it carries any flux, isotropic otherwise
         const R m = fmax(fabs(Fx), fmax(fabs(Fy), fabs(Fz)));
-        if (m > R(0)) {
+        p.dir = m > R(0);
+        if (p.dir) {
             const R im = rcp(m);
             const R bx = Fx * im, by = Fy * im, bz = Fz * im;
-            f = R(1);
-            ct = (Fd * im) * rcp(sqrt(bx * bx + by * by + bz * bz));
+            p.f = R(1);
+            p.num[0] = bx;
+            p.num[1] = by;
+            p.num[2] = bz;
+            p.q = rcp(sqrt(bx * bx + by * by + bz * bz));
         } else {
-            f = R(0);
-            ct = R(1);
+            p.f = R(0);
+            p.num[0] = p.num[1] = p.num[2] = R(0);
+            p.q = R(1);
         }
     }
+    const R uf = p.f * R(nf - 1);
+    int i = (int)floor(uf);
+    p.i = i > nf - 2 ? nf - 2 : (i < 0 ? 0 : i);
+    p.wf = uf - R(p.i);
+    return p;
+}
+
+template <typename R>
+__device__ __forceinline__ void hll_axis(const R *__restrict__ tab, int nth, const HllPrep<R> &p, int d, R &lmin,
+                                         R &lmax)
+{
+    R ct = p.dir ? p.num[d] * p.q : R(1);
     ct = ct > R(1) ? R(1) : (ct < R(-1) ? R(-1) : ct);
     const R th = acos(ct);
-    const R uf = f * R(nf - 1);
     const R ut = th * R(0.31830988618379067154) * R(nth - 1);
-    int i = (int)floor(uf), k = (int)floor(ut);
-    i = i > nf - 2 ? nf - 2 : (i < 0 ? 0 : i);
+    int k = (int)floor(ut);
     k = k > nth - 2 ? nth - 2 : (k < 0 ? 0 : k);
-    const R wf = uf - R(i), wt = ut - R(k);
-    const R *t00 = tab + ((size_t)i * nth + k) * 2;
+    const R wf = p.wf, wt = ut - R(k);
+    const R *t00 = tab + ((size_t)p.i * nth + k) * 2;
     const R *t01 = t00 + 2;
     const R *t10 = t00 + (size_t)nth * 2;
     const R *t11 = t10 + 2;
     const R a00 = (R(1) - wf) * (R(1) - wt), a10 = wf * (R(1) - wt), a01 = (R(1) - wf) * wt, a11 = wf * wt;
     lmin = a00 * t00[0] + a10 * t10[0] + a01 * t01[0] + a11 * t11[0];
     lmax = a00 * t00[1] + a10 * t10[1] + a01 * t01[1] + a11 * t11[1];
-    const R a = f * ct;
+    const R a = p.f * ct;
     lmin = lmin < a ? lmin : a;
     lmax = lmax > a ? lmax : a;
+}
+
+template <typename R>
+__device__ __forceinline__ void hll_speeds(const R *__restrict__ tab, int nf, int nth, R N, R Fx, R Fy,
+                                           R Fz, int d, R c, R &lmin, R &lmax)
+{
+    const HllPrep<R> p = hll_prep(nf, N, Fx, Fy, Fz, c);
+    hll_axis(tab, nth, p, d, lmin, lmax);
 }
 
 // ---------------------------------------------------------------------

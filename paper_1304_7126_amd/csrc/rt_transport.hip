@@ -38,7 +38,7 @@ __device__ __forceinline__ void side_of(const R *__restrict__ tab, int nf, int n
     m1_pressure(u.n, u.fx, u.fy, u.fz, c, s.p);
     s.lm = R(0);
     s.lp = R(0);
-    if (FLUX == 1) hll_speeds(tab, nf, nth, u.n, u.fx, u.fy, u.fz, comp(u, d), c, s.lm, s.lp);
+    if (FLUX == 1) hll_speeds(tab, nf, nth, u.n, u.fx, u.fy, u.fz, d, c, s.lm, s.lp);
 }
 
 // A cell's closure and its wave speeds along all three axes.
@@ -59,7 +59,12 @@ __device__ __forceinline__ void eval_cell(const R *__restrict__ tab, int nf, int
     for (int d = 0; d < 3; ++d) {
         e.lm[d] = R(0);
         e.lp[d] = R(0);
-        if (FLUX == 1) hll_speeds(tab, nf, nth, u.n, u.fx, u.fy, u.fz, comp(u, d), c, e.lm[d], e.lp[d]);
+    }
+    if (FLUX == 1) {
+        // the table row and the flux direction are shared by the three axes
+        const HllPrep<R> hp = hll_prep(nf, u.n, u.fx, u.fy, u.fz, c);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) hll_axis(tab, nth, hp, d, e.lm[d], e.lp[d]);
     }
 }
 
