@@ -136,32 +136,30 @@ __device__ __forceinline__ HllPrep<R> hll_prep(int nf, R N, R Fx, R Fy, R Fz, R 
 {
     HllPrep<R> p;
     const R icN = rcp(c * N);
+    const R m = fmax(fabs(Fx), fmax(fabs(Fy), fabs(Fz)));
+    p.dir = m > R(0);
     if (N > R(0) && !isinf(icN)) {
         const R ax = Fx * icN, ay = Fy * icN, az = Fz * icN;
         const R an = sqrt(ax * ax + ay * ay + az * az);
         p.f = an > R(1) ? R(1) : an;
-        p.dir = an > R(0);
-        p.num[0] = ax;
-        p.num[1] = ay;
-        p.num[2] = az;
-        p.q = p.dir ? rcp(an) : R(1);
     } else {
         // empty cell: a beam if it carries any flux, isotropic otherwise
-        const R m = fmax(fabs(Fx), fmax(fabs(Fy), fabs(Fz)));
-        p.dir = m > R(0);
-        if (p.dir) {
-            const R im = rcp(m);
-            const R bx = Fx * im, by = Fy * im, bz = Fz * im;
-            p.f = R(1);
-            p.num[0] = bx;
-            p.num[1] = by;
-            p.num[2] = bz;
-            p.q = rcp(sqrt(bx * bx + by * by + bz * bz));
-        } else {
-            p.f = R(0);
-            p.num[0] = p.num[1] = p.num[2] = R(0);
-            p.q = R(1);
-        }
+        p.f = p.dir ? R(1) : R(0);
+    }
+    // Direction cosines of F from F scaled by its largest component.  A flux
+    // of subnormal size (FP32 fronts reach them) is first scaled by 2^64,
+    // exactly, so that the reciprocal of that component cannot overflow.
+    if (p.dir) {
+        const R up = m < R(8.673617379884035e-19) ? R(18446744073709551616.0) : R(1);  // 2^-60, 2^64
+        const R im = rcp(m * up);
+        const R bx = (Fx * up) * im, by = (Fy * up) * im, bz = (Fz * up) * im;
+        p.num[0] = bx;
+        p.num[1] = by;
+        p.num[2] = bz;
+        p.q = rcp(sqrt(bx * bx + by * by + bz * bz));
+    } else {
+        p.num[0] = p.num[1] = p.num[2] = R(0);
+        p.q = R(1);
     }
     const R uf = p.f * R(nf - 1);
     int i = (int)floor(uf);

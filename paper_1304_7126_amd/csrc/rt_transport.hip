@@ -177,7 +177,11 @@ __device__ __forceinline__ void block_sum2(double a, double b, double &sa, doubl
     rs[0][t] = a;
     rs[1][t] = b;
     __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
+    // halve from the power of two at or above n: slots [o, 2o) are added
+    // into [0, o), in the same order on every run
+    int p2 = 1;
+    while (p2 < n) p2 <<= 1;
+    for (int o = p2 / 2; o > 0; o >>= 1) {
         if (t < o && t + o < n) {
             rs[0][t] += rs[0][t + o];
             rs[1][t] += rs[1][t + o];

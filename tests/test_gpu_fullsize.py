@@ -82,14 +82,20 @@ def sample_cells(w, ijk, natt_prev, nsample, seed):
 
 def perturbed_oracle(o, pre, dt, cells, eps, seed=1, N_pre=None):
     """The oracle's step of the sampled cells from the injected pre-step
-    state with every N and F value scaled by (1 +- eps) (random signs): the
-    spread of the result measures how strongly the step amplifies a
-    relative perturbation of its input of that size."""
+    state with every N and F value scaled by 1 +- eps, once with random signs
+    and once all by 1 + eps (rounding that is the same across a stencil, as
+    that of the FP32 constants): the spread of the results measures how
+    strongly the step amplifies a relative perturbation of its input of
+    that size."""
     rng = np.random.default_rng(seed)
-    p = dict(pre)
-    p["N"] = pre["N"] * (1 + eps * rng.choice([-1.0, 1.0], pre["N"].shape))
-    p["F"] = pre["F"] * (1 + eps * rng.choice([-1.0, 1.0], pre["F"].shape))
-    return o.step_cells(p, dt, cells, N_pre=N_pre)
+    out = []
+    for signs in ("random", "same"):
+        p = dict(pre)
+        for k in ("N", "F"):
+            sg = rng.choice([-1.0, 1.0], pre[k].shape) if signs == "random" else 1.0
+            p[k] = pre[k] * (1 + eps * sg)
+        out.append(o.step_cells(p, dt, cells, N_pre=N_pre))
+    return out
 
 
 def compare_sampled(w, pre, g, cells, r, tol, spread=None, K=10.0, dark=None, abs_floor=0.0):
@@ -99,9 +105,9 @@ def compare_sampled(w, pre, g, cells, r, tol, spread=None, K=10.0, dark=None, ab
     Cells whose accepted-substep and attempt counts match the oracle's are
     compared field by field; the others (a 10%-rule decision taken on the
     other side of its threshold) are counted.  With `spread` (the oracle's
-    result from an input perturbed by the rounding of the GPU's transport
+    results from inputs perturbed by the rounding of the GPU's transport
     precision, see perturbed_oracle) every limit grows by K times the
-    oracle's own change, and cells whose counts that perturbation changes
+    oracle's largest change, and cells whose counts a perturbation changes
     may also change on the GPU.  With `dark`, cells where some group's
     photon density is below it over the whole 7-point stencil (densities at
     the bottom of the floating-point range of the transport, whose rounding
@@ -126,11 +132,11 @@ def compare_sampled(w, pre, g, cells, r, tol, spread=None, K=10.0, dark=None, ab
             m = np.maximum(m, Ng[(iz + dz) % nz, (iy + dy) % ny, (ix + dx_) % nx])
         nstencil.append(m)
     ds = {k: np.zeros_like(v, dtype=np.float64) for k, v in r.items() if k in ("N", "F", "x", "T")}
-    if spread is not None:
-        ds = {k: K * np.abs(spread[k] - r[k]) for k in ds}
     free = np.zeros_like(same)
-    if spread is not None:
-        free |= (spread["nacc"] != r["nacc"]) | (spread["natt"] != r["natt"])
+    for sp in spread or ():
+        for k in ds:
+            ds[k] = np.maximum(ds[k], K * np.abs(sp[k] - r[k]))
+        free |= (sp["nacc"] != r["nacc"]) | (sp["natt"] != r["natt"])
     if dark is not None:
         dk = np.any(np.stack(nstencil, axis=1) < dark, axis=1)
         fd = ~same & dk

@@ -399,3 +399,37 @@ def test_transport_subnormal_densities_stay_finite():
     g = ctx.state_numpy()
     assert np.all(np.isfinite(g["N"])) and np.all(np.isfinite(g["F"]))
     assert (ctx.stats()["flags"] & 2) == 0
+
+
+@pytest.mark.parametrize("flux", [1, 0])
+def test_transport_fp32_empty_cells_with_subnormal_flux(flux):
+    # Fronts in dense gas leave empty cells whose flux components are FP32
+    # subnormals.  Their direction must still come out right (the reciprocal
+    # of a subnormal overflows in FP32): the transport of their neighbours
+    # matches the oracle to the FP32 bound on the local radiation scale.
+    rng = np.random.default_rng(43)
+    n = (29, 17, 11)
+    ctx, o = make_pair(n, BCS[0], 2, flux, fp32=True)
+    N, F = random_rad(n, 2, rng, empty_frac=0.0)
+    empty = rng.uniform(size=N.shape) < 0.4
+    N[empty] = 0.0
+    tiny = 10.0 ** rng.uniform(-44.5, -38.5, F.shape) * rng.choice([-1.0, 1.0], F.shape)
+    F = np.where(empty[:, None], tiny, F)
+    N = N.astype(np.float32).astype(np.float64)
+    F = F.astype(np.float32).astype(np.float64)
+    st = {"N": N, "F": F, **gas(n, rng)}
+    ctx.load_state(st)
+    dt = ctx.courant_dt()
+    ctx.transport(dt)
+    o.transport(st, dt)
+    g = ctx.state_numpy()
+    for gi in range(2):
+        # scale: the largest density of each cell's 7-point periodic stencil
+        Ng = N[gi]
+        m = Ng.copy()
+        for ax in range(3):
+            m = np.maximum(m, np.maximum(np.roll(Ng, 1, ax), np.roll(Ng, -1, ax)))
+        errN = np.abs(g["N"][gi] - st["N"][gi])
+        assert np.all(errN <= 1e-5 * m + 1e-37), (gi, errN.max())
+        errF = np.linalg.norm(g["F"][gi] - st["F"][gi], axis=0)
+        assert np.all(errF <= 1e-5 * C_R * m + 1e-37), (gi, errF.max())
