@@ -142,7 +142,10 @@ typedef struct {
  *         partials, the queue of cells still subcycling after the first
  *         chemistry pass, accounting partials and each cell's attempt count
  *         of the previous pass (which orders the queue; rt_bind clears it).
- *         Required; the library owns its contents while it is bound. */
+ *         The library owns its contents while it is bound.  May be NULL
+ *         (with scratch_bytes = 0) for a context stepped only with
+ *         rt_step_noalloc: rt_step, rt_thermochem, rt_get_stats and the
+ *         accounting then return RT_ESTATE. */
 typedef struct {
     void *N[2];
     void *F[2];
@@ -250,6 +253,22 @@ rt_status rt_thermochem(rt_ctx *ctx, double dt);
  * bit for bit, whichever transport kernel runs (rt_set_transport_path).
  * dt <= 0 uses the Courant step with factor 0.8. */
 rt_status rt_step(rt_ctx *ctx, double dt, int nsteps);
+
+/* rt_step without the bound scratch, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the state must be bound (rt_bind
+ * accepts scratch = NULL, scratch_bytes = 0), and the reduction partials,
+ * the chemistry queue, the accounting partials and the previous pass's
+ * attempt counts go to a static device array of 64 MiB that the library
+ * holds on every GPU it runs on until the process ends.  The queue takes
+ * what the array has left (cells beyond it finish in the first chemistry
+ * pass); results are the bits rt_step gives.  Allocates nothing and makes
+ * no timing events.  RT_EINVAL when the grid needs more than the array
+ * (about 1 + 48/256 bytes per cell besides the queue: up to ~56 M cells),
+ * RT_EUNSUPPORTED with smooth = 1.  Every call on a GPU shares its array and
+ * leaves its contents behind: calls that overlap on one GPU (two contexts on
+ * two streams) race and must be serialised by the caller. */
+rt_status rt_step_noalloc(rt_ctx *ctx, double dt, int nsteps);
 
 /* Kernel arrangement of the transport (Sec. 3.2); results are the same bits
  * on every path:

@@ -26,7 +26,7 @@ EXPORTED = [
     "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
     "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint", "rt_set_accounting",
-    "rt_set_inflow", "rt_set_expansion",
+    "rt_set_inflow", "rt_set_expansion", "rt_step_noalloc",
 ]
 
 
@@ -118,6 +118,8 @@ def lib():
         f.argtypes = [vp, ctypes.c_double]
         f.restype = st
     L.rt_step.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+    L.rt_step_noalloc.argtypes = [vp, ctypes.c_double, ctypes.c_int]
+    L.rt_step_noalloc.restype = st
     L.rt_step.restype = st
     L.rt_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
     L.rt_set_tuning.restype = st

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,7 @@
 using namespace rtm1;
 
 struct rt_ctx {
+    int device = 0;            // the HIP device current at rt_init
     KGrid grid;
     rt_groups groups;
     rt_params params;
@@ -131,6 +133,33 @@ static thread_local std::string g_init_err;
         if (_e != hipSuccess)                                                                      \
             RT_FAIL(ctx, RT_EHIP, "%s failed: %s", #call, hipGetErrorString(_e));                 \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Scratch of rt_step_noalloc: one file-scope device array of a fixed size;
+// every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel (on the host it
+// stands for no device address): rt_init looks up its address on the
+// context's device once per device and keeps it in g_noalloc_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_noalloc_mu;
+
+// the address of this device's array (looked up on first use of the device)
+static hipError_t noalloc_setup(int dev)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[dev]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = ptr;
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // HLL eigenvalue table (Sec. 3.2).  Extreme eigenvalues of the M1 flux
@@ -372,7 +401,17 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
         g_init_err = err;
         return v;
     }
+    int dev = 0;
+    {
+        hipError_t e0 = hipGetDevice(&dev);
+        if (e0 == hipSuccess) e0 = noalloc_setup(dev);
+        if (e0 != hipSuccess) {
+            g_init_err = std::string("device set-up failed: ") + hipGetErrorString(e0);
+            return RT_EHIP;
+        }
+    }
     rt_ctx *c = new rt_ctx();
+    c->device = dev;
     c->grid.nx = grid->nx;
     c->grid.ny = grid->ny;
     c->grid.nz = grid->nz;
@@ -492,14 +531,15 @@ extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
     if (!s->N[0] || !s->N[1] || !s->F[0] || !s->F[1]) RT_FAIL(c, RT_EINVAL, "radiation buffers must be non-null");
     if (s->N[0] == s->N[1] || s->F[0] == s->F[1]) RT_FAIL(c, RT_EINVAL, "the two radiation sets must differ");
     if (!s->xHII || !s->xHeII || !s->xHeIII || !s->T || !s->nH) RT_FAIL(c, RT_EINVAL, "gas arrays must be non-null");
-    if (!s->scratch || s->scratch_bytes < scratch_need(c))
+    if (s->scratch && s->scratch_bytes < scratch_need(c))
         RT_FAIL(c, RT_EINVAL, "scratch must hold rt_scratch_bytes() = %zu bytes", scratch_need(c));
+    if (!s->scratch && s->scratch_bytes != 0) RT_FAIL(c, RT_EINVAL, "null scratch with a nonzero size");
     c->st = *s;
     c->bound = true;
     c->cur = 0;
     c->sm_phase = 0;
     // no previous pass yet: every count starts at zero
-    RT_HIP(c, hipMemset(prev_att(c), 0, c->grid.ncell));
+    if (c->st.scratch) RT_HIP(c, hipMemset(prev_att(c), 0, c->grid.ncell));
     return RT_OK;
 }
 
@@ -636,6 +676,13 @@ static rt_status check_ready(rt_ctx *c, double dt)
 {
     if (!c->bound) RT_FAIL(c, RT_ESTATE, "no state bound");
     if (!(dt > 0) || !std::isfinite(dt)) RT_FAIL(c, RT_EINVAL, "dt must be positive and finite");
+    return RT_OK;
+}
+
+// the chemistry passes, the accounting and the diagnostics work in scratch
+static rt_status need_scratch(rt_ctx *c)
+{
+    if (!c->st.scratch) RT_FAIL(c, RT_ESTATE, "no scratch bound (bind rt_scratch_bytes() of scratch, or use rt_step_noalloc)");
     return RT_OK;
 }
 
@@ -798,6 +845,7 @@ extern "C" rt_status rt_transport(rt_ctx *c, double dt)
     if (!c) return RT_EINVAL;
     rt_status r = check_ready(c, dt);
     if (r != RT_OK) return r;
+    if (c->acct && (r = need_scratch(c)) != RT_OK) return r;
     return do_transport(c, dt);
 }
 
@@ -806,16 +854,13 @@ extern "C" rt_status rt_thermochem(rt_ctx *c, double dt)
     if (!c) return RT_EINVAL;
     rt_status r = check_ready(c, dt);
     if (r != RT_OK) return r;
+    if ((r = need_scratch(c)) != RT_OK) return r;
     return do_chem(c, dt);
 }
 
-extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
+static rt_status step_loop(rt_ctx *c, double dt, int nsteps)
 {
-    if (!c) return RT_EINVAL;
-    if (nsteps < 0) RT_FAIL(c, RT_EINVAL, "nsteps < 0");
-    if (!(dt > 0)) dt = 0.8 * dt_limit(c);
-    rt_status r = check_ready(c, dt);
-    if (r != RT_OK) return r;
+    rt_status r = RT_OK;
     const bool zm = use_zmarch(c);
     for (int k = 0; k < nsteps; ++k) {
         if ((r = do_inject(c, dt)) != RT_OK) return r;
@@ -828,6 +873,74 @@ extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
         }
     }
     return RT_OK;
+}
+
+extern "C" rt_status rt_step(rt_ctx *c, double dt, int nsteps)
+{
+    if (!c) return RT_EINVAL;
+    if (nsteps < 0) RT_FAIL(c, RT_EINVAL, "nsteps < 0");
+    if (!(dt > 0)) dt = 0.8 * dt_limit(c);
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    if ((r = need_scratch(c)) != RT_OK) return r;
+    return step_loop(c, dt, nsteps);
+}
+
+// rt_step in the device's static scratch array: the same launches with the
+// reduction partials, the chemistry queue (of the capacity that fits; cells
+// beyond it finish in the first pass, which leaves results unchanged), the
+// accounting partials and the previous-pass attempt counts laid out there.
+extern "C" rt_status rt_step_noalloc(rt_ctx *c, double dt, int nsteps)
+{
+    if (!c) return RT_EINVAL;
+    if (nsteps < 0) RT_FAIL(c, RT_EINVAL, "nsteps < 0");
+    if (!(dt > 0)) dt = 0.8 * dt_limit(c);
+    rt_status r = check_ready(c, dt);
+    if (r != RT_OK) return r;
+    if (c->params.smooth) RT_FAIL(c, RT_EUNSUPPORTED, "rt_step_noalloc: smoothed RT is not supported");
+    void *ptr = (c->device >= 0 && c->device < NOALLOC_MAX_DEVICES) ? g_noalloc_ptr[c->device] : nullptr;
+    if (!ptr) RT_FAIL(c, RT_ESTATE, "rt_step_noalloc: no static scratch on device %d", c->device);
+    // the layout with an empty queue, then as many queue cells as fit
+    const unsigned save_cap = c->qcap, save_max = c->qcap_max;
+    c->qcap = c->qcap_max = 0;
+    const size_t fixed = scratch_need(c);
+    c->qcap = save_cap;
+    c->qcap_max = save_max;
+    if (fixed > NOALLOC_SCRATCH_BYTES)
+        RT_FAIL(c, RT_EINVAL, "rt_step_noalloc: the grid needs %zu bytes of scratch, more than the %zu-byte static buffer",
+                fixed, NOALLOC_SCRATCH_BYTES);
+    const size_t spare = NOALLOC_SCRATCH_BYTES - fixed;
+    size_t cap = spare > 512 ? (spare - 512) / queue_cell_bytes(false) : 0;
+    if (cap > c->grid.ncell) cap = c->grid.ncell;
+    // swap the static layout in (no timing: its events would be created)
+    void *save_scr = c->st.scratch;
+    const size_t save_bytes = c->st.scratch_bytes;
+    const bool save_timing = c->timing;
+    c->st.scratch = ptr;
+    c->st.scratch_bytes = NOALLOC_SCRATCH_BYTES;
+    c->qcap = c->qcap_max = (unsigned)cap;
+    c->timing = false;
+    if (scratch_need(c) > NOALLOC_SCRATCH_BYTES) {
+        r = RT_EINVAL;
+        c->err = "rt_step_noalloc: layout exceeds the static buffer";
+    } else {
+        // the array keeps the last call's contents: clear the attempt counts
+        // that order the queue (the counters and partials are reset or
+        // overwritten by the step's own kernels)
+        const hipError_t e = launch_fill_u8(prev_att(c), c->grid.ncell, 0, c->stream);
+        if (e != hipSuccess) {
+            r = RT_EHIP;
+            c->err = std::string("rt_step_noalloc: ") + hipGetErrorString(e);
+        } else {
+            r = step_loop(c, dt, nsteps);
+        }
+    }
+    c->st.scratch = save_scr;
+    c->st.scratch_bytes = save_bytes;
+    c->qcap = save_cap;
+    c->qcap_max = save_max;
+    c->timing = save_timing;
+    return r;
 }
 
 extern "C" rt_status rt_set_transport_path(rt_ctx *c, int path)
@@ -844,6 +957,7 @@ extern "C" rt_status rt_get_stats(rt_ctx *c, rt_stats *out)
 {
     if (!c || !out) return RT_EINVAL;
     if (!c->bound) RT_FAIL(c, RT_ESTATE, "no state bound");
+    if (need_scratch(c) != RT_OK) return RT_ESTATE;
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
     RT_HIP(c, launch_reduce(c->fp32, c->grid.ncell, c->groups.M, c->groups.c_r, V, c->st.N[c->cur], c->st.F[c->cur],
                             c->st.xHII, c->st.nH, c->st.scratch, c->dred, c->stream));

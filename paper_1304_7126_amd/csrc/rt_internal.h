@@ -66,6 +66,9 @@ size_t reduction_scratch_bytes();
 hipError_t launch_inject(bool fp32, void *N, size_t ncell, int M, int nsrc, const int32_t *cell,
                          const double *rate, double dt_over_V, double *prev, hipStream_t s);
 
+// p[0..n) = v with a kernel (no memset node in a captured graph)
+hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t s);
+
 // map[cell] = index of the source in that cell, -1 elsewhere
 hipError_t launch_source_map(int32_t *map, size_t ncell, const int32_t *cell, int nsrc, hipStream_t s);
 
@@ -153,6 +156,8 @@ constexpr int HEAD_ATTEMPTS = 3;
 // bytes of scratch for a queue of cap cells (after the reduction partials),
 // laid out for smoothed RT when smooth is set
 size_t queue_bytes(unsigned cap, bool smooth);
+// bytes one queued cell takes (without the alignment of the layout)
+size_t queue_cell_bytes(bool smooth);
 // cap: cells the kernels may queue; layout_cap: capacity the scratch is laid out for
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
 

@@ -53,6 +53,19 @@ __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v)
     if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_u8(uint8_t *p, size_t n, uint8_t v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 __global__ void k_source_map(int32_t *map, const int32_t *__restrict__ cell, int nsrc)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -542,6 +555,8 @@ size_t queue_bytes(unsigned cap, bool smooth)
     return 512 + align256((size_t)cap * 3 * sizeof(int32_t)) +
            (size_t)(smooth ? QV_SMOOTH : QV_GRID) * cap * sizeof(double);
 }
+
+size_t queue_cell_bytes(bool smooth) { return 3 * sizeof(int32_t) + (size_t)(smooth ? QV_SMOOTH : QV_GRID) * sizeof(double); }
 
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
 {

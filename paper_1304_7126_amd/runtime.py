@@ -58,7 +58,7 @@ class RTContext:
 
     def __init__(self, n, dx, bc, M, c_r, sigN, sigE, ebar, flux=0, isothermal=False, X=0.76, Y=0.24,
                  gamma=5.0 / 3.0, a_exp=1.0, x_min=1e-6, N_floor=0.0, max_attempts=100000, fp32=False,
-                 device="cuda", counters=False, smooth=False, otsa=True, brec=(-1, -1, -1)):
+                 device="cuda", counters=False, smooth=False, otsa=True, brec=(-1, -1, -1), scratch=True):
         L = lib()
         g = capi.RtGrid()
         g.nx, g.ny, g.nz = (int(v) for v in n)
@@ -111,8 +111,9 @@ class RTContext:
         self.nH = torch.zeros_like(self.xHII)
         self.nacc = torch.zeros((nz, ny, nx), dtype=torch.int32, device=dev) if counters else None
         self.natt = torch.zeros_like(self.nacc) if counters else None
+        # scratch=False: no scratch buffer (the context steps with step_noalloc)
         sb = int(L.rt_scratch_bytes(h))
-        self.scratch = torch.zeros(max(sb, 256), dtype=torch.uint8, device=dev)
+        self.scratch = torch.zeros(max(sb, 256), dtype=torch.uint8, device=dev) if scratch else None
         self._bind()
         self.set_stream(torch.cuda.current_stream(dev))
 
@@ -145,8 +146,8 @@ class RTContext:
         s.nH = self.nH.data_ptr()
         s.nacc = self.nacc.data_ptr() if self.nacc is not None else None
         s.natt = self.natt.data_ptr() if self.natt is not None else None
-        s.scratch = self.scratch.data_ptr()
-        s.scratch_bytes = self.scratch.numel()
+        s.scratch = self.scratch.data_ptr() if self.scratch is not None else None
+        s.scratch_bytes = self.scratch.numel() if self.scratch is not None else 0
         check(lib().rt_bind(self._h, ctypes.byref(s)), self._h)
 
     def set_stream(self, stream):
@@ -200,6 +201,10 @@ class RTContext:
 
     def step(self, dt=0.0, nsteps=1):
         check(lib().rt_step(self._h, float(dt), int(nsteps)), self._h)
+
+    def step_noalloc(self, dt=0.0, nsteps=1):
+        """rt_step in the library's static per-GPU scratch (no allocation)."""
+        check(lib().rt_step_noalloc(self._h, float(dt), int(nsteps)), self._h)
 
     # ------------------------------------------------------------ results
     @property
