@@ -140,8 +140,10 @@ typedef struct {
  *         of attempts in the last thermochemistry pass (NULL: not written)
  *   scratch  device buffer of at least rt_scratch_bytes() bytes: reduction
  *         partials, the queue of cells still subcycling after the first
- *         chemistry pass, accounting partials and each cell's attempt count
- *         of the previous pass (which orders the queue; rt_bind clears it).
+ *         chemistry pass, accounting partials, each cell's attempt count
+ *         of the previous pass (which orders the queue; rt_bind clears it)
+ *         and, with smooth = 1, each cell's source index (rt_bind and
+ *         rt_set_sources write it).
  *         The library owns its contents while it is bound.  May be NULL
  *         (with scratch_bytes = 0) for a context stepped only with
  *         rt_step_noalloc: rt_step, rt_thermochem, rt_get_stats and the
@@ -325,10 +327,13 @@ rt_status rt_build_hll_table(int nf, int nth, double *out);
  * launch of the step is bracketed by events; rt_get_timing synchronises the
  * stream and returns the accumulated milliseconds and launch counts per
  * kernel class, then clears them.  Disabled by default. */
+#define RT_TIMING_CLASSES 6
 typedef struct {
-    double ms[5];       /* inject, transport, chemistry head (fused with
-                           transport in rt_step), chemistry tail, other */
-    long long launches[5];
+    double ms[RT_TIMING_CLASSES];  /* inject, transport, chemistry head (fused
+                                      with transport on the per-cell path),
+                                      chemistry tail, other (adjoint passes),
+                                      photon accounting (reductions, ledger) */
+    long long launches[RT_TIMING_CLASSES];
 } rt_timing;
 rt_status rt_set_timing(rt_ctx *ctx, int enabled);
 rt_status rt_get_timing(rt_ctx *ctx, rt_timing *out);
@@ -371,6 +376,10 @@ rt_status rt_batch_set_current(rt_batch *b, int set);
 /* Sources of one box, as rt_set_sources (ndot[s*M_box + g]). */
 rt_status rt_batch_set_sources(rt_batch *b, int box, int n, const int32_t *ijk, const double *ndot);
 
+/* Courant-limited step of the batch (Sec. 4.1, eq. dt_courant): courant x
+ * dx_min / (3 c_r), the finest box setting the common step (courant > 0). */
+rt_status rt_batch_courant_dt(const rt_batch *b, double courant, double *dt);
+
 /* nsteps steps of every box; dt <= 0 uses 0.8 dx_min/(3 c_r).  dt must
  * satisfy the Courant limit of the finest box. */
 rt_status rt_batch_step(rt_batch *b, double dt, int nsteps);
@@ -396,7 +405,11 @@ void rt_batch_free(rt_batch *b);
  *
  * Supported configuration (RT_EUNSUPPORTED otherwise): one photon group,
  * hydrogen-only gas (Y = 0), GLF flux, periodic boundaries on all faces,
- * RT_PREC_FP64.  Isothermal and temperature-evolving gas are both supported.
+ * no smoothing, OTSA, static box.  Isothermal and temperature-evolving gas
+ * are both supported, and both precisions: with RT_PREC_FP32_TRANSPORT the forward
+ * steps are the mixed form's (FP32 N and F), the tape holds them widened to
+ * FP64 and the adjoint runs in FP64, so the result is the gradient of the
+ * mixed form's own forward map.
  *
  * Of step k (U_k -> injection -> U_a -> transport -> U_b -> chemistry ->
  * U_k+1) the adjoint applies the transposes of
@@ -415,7 +428,8 @@ void rt_batch_free(rt_batch *b);
  * --------------------------------------------------------------------- */
 
 /* Per-step tape, caller-owned device memory.
- *   Na      ncell doubles: N after the step's injection (the transport input)
+ *   Na      ncell doubles: N after the step's injection (the transport input;
+ *           with RT_PREC_FP32_TRANSPORT the FP32 values, widened)
  *   Fa      3*ncell doubles: F after injection, layout [axis][cell]
  *   counts  ncell int32: accepted chemistry substeps of each cell in this
  *           step, as rt_step writes them to rt_state.nacc (input)

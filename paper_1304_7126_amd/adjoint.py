@@ -4,7 +4,8 @@ the hand-written adjoint kernels of librtm1.so (rt_step_record,
 rt_step_adjoint), with step checkpointing, behind a torch.autograd.Function.
 
 Setting of the adjoint: hydrogen-only gas, one photon group, GLF transport,
-periodic box, FP64 (the library refuses anything else).
+periodic box (the library refuses anything else); FP64 state or the mixed
+form's FP32 radiation, whose gradient is that of the mixed forward map.
 
 Forward: `steps` calls of rt_step, a copy of the state every `every` steps
 (the checkpoints) and of each step's per-cell substep counts.  Backward,
@@ -37,8 +38,8 @@ class GradientRun:
     def __init__(self, ctx, ijk, dt: float, steps: int, x0: float, T0: float, every: int = 20):
         if ctx.nacc is None:
             raise ValueError("the RTContext needs counters=True (per-cell substep counts)")
-        if ctx.M != 1 or ctx.fp32:
-            raise ValueError("the adjoint needs one photon group and FP64 state")
+        if ctx.M != 1:
+            raise ValueError("the adjoint needs one photon group")
         self.ctx = ctx
         self.ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
         self.dt = float(dt)
@@ -51,6 +52,10 @@ class GradientRun:
         self.ckpt = []
         self.off_len = int(lib().rt_tape_offsets_len(ctx._h))
         self.last_backward = {}
+        # the forward run the checkpoints and counts belong to: its number
+        # and its parameters, which backward() sets again before re-running
+        self.forward_id = 0
+        self.params = None
 
     # ------------------------------------------------------------ forward
     def _set_params(self, lnNdot: torch.Tensor, lnnH: torch.Tensor):
@@ -89,6 +94,8 @@ class GradientRun:
         self._set_params(lnNdot, lnnH)
         self._initial_state()
         self.ckpt = []
+        self.forward_id += 1
+        self.params = (lnNdot.detach().clone(), lnnH.detach().clone())
         for k in range(self.steps):
             if k % self.every == 0:
                 self.ckpt.append(self._snapshot())
@@ -133,10 +140,20 @@ class GradientRun:
         return ctx.xHII.clone()
 
     # ----------------------------------------------------------- backward
-    def backward(self, grad_x: torch.Tensor, grad_T: Optional[torch.Tensor] = None):
+    def backward(self, grad_x: torch.Tensor, grad_T: Optional[torch.Tensor] = None,
+                 forward_id: Optional[int] = None):
         """dL/dln Ndot (K,) and dL/dln n_H (nz, ny, nx) for dL/dx_HII = grad_x
-        (and dL/dT = grad_T) at the end of the run."""
+        (and dL/dT = grad_T) at the end of the last forward run, at that
+        run's parameters (set again here, whatever the context holds now).
+        With forward_id, raises RTError unless the checkpoints still belong
+        to that forward run."""
+        if self.params is None:
+            raise capi.RTError("backward before any forward run")
+        if forward_id is not None and forward_id != self.forward_id:
+            raise capi.RTError(f"the checkpoints of forward run {forward_id} were replaced by forward run "
+                               f"{self.forward_id}")
         ctx = self.ctx
+        self._set_params(*self.params)
         L = lib()
         dev = ctx.device
         nc = self.nc
@@ -191,11 +208,13 @@ class RTRun(torch.autograd.Function):
     def forward(fctx, lnNdot, lnnH, run: GradientRun):
         fctx.run = run
         fctx.src_device = lnNdot.device
-        return run.forward(lnNdot, lnnH)
+        x = run.forward(lnNdot, lnnH)
+        fctx.forward_id = run.forward_id
+        return x
 
     @staticmethod
     def backward(fctx, grad_x):
-        g_src, g_nH = fctx.run.backward(grad_x)[:2]
+        g_src, g_nH = fctx.run.backward(grad_x, forward_id=fctx.forward_id)[:2]
         return g_src.to(fctx.src_device), g_nH, None
 
 

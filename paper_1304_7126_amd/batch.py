@@ -114,7 +114,9 @@ class RTBatch:
                                          int(use_graph)), self._h)
 
     def courant_dt(self, courant=0.8):
-        return courant * min(self.dx) / (3.0 * self.c_r)
+        v = ctypes.c_double()
+        _check(lib().rt_batch_courant_dt(self._h, float(courant), ctypes.byref(v)), self._h)
+        return v.value
 
     def step(self, dt=0.0, nsteps=1):
         torch.cuda.current_stream(self.device).synchronize()

@@ -23,7 +23,7 @@ EXPORTED = [
     "rt_get_stats", "rt_reset_stats", "rt_group_attributes", "rt_hll_table", "rt_build_hll_table",
     "rt_last_error", "rt_free", "rt_set_tuning", "rt_set_transport_path", "rt_set_timing", "rt_get_timing",
     "rt_batch_init", "rt_batch_scratch_bytes", "rt_batch_bind", "rt_batch_set_stream", "rt_batch_current",
-    "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
+    "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_courant_dt", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
     "rt_tape_offsets_len", "rt_step_record", "rt_step_replay", "rt_step_adjoint", "rt_set_accounting",
     "rt_set_inflow", "rt_set_expansion", "rt_step_noalloc",
@@ -65,11 +65,11 @@ class RtStats(ctypes.Structure):
                 ("outflow", ctypes.c_double * 3), ("substep_hist", ctypes.c_longlong * 64)]
 
 
+TIMING_CLASSES = ("inject", "transport", "head", "tail", "other", "accounting")
+
+
 class RtTiming(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_longlong * 5)]
-
-
-TIMING_CLASSES = ("inject", "transport", "head", "tail", "other")
+    _fields_ = [("ms", ctypes.c_double * len(TIMING_CLASSES)), ("launches", ctypes.c_longlong * len(TIMING_CLASSES))]
 
 
 class RtTape(ctypes.Structure):
@@ -166,6 +166,8 @@ def lib():
     L.rt_batch_set_current.restype = st
     L.rt_batch_set_sources.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), dp]
     L.rt_batch_set_sources.restype = st
+    L.rt_batch_courant_dt.argtypes = [vp, ctypes.c_double, dp]
+    L.rt_batch_courant_dt.restype = st
     L.rt_batch_step.argtypes = [vp, ctypes.c_double, ctypes.c_int]
     L.rt_batch_step.restype = st
     L.rt_batch_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]

@@ -1,6 +1,9 @@
 // rt_adjoint.hip -- kernels of the differentiation form: the reverse
 // (adjoint) pass of the RT step for hydrogen-only gas, one photon group,
-// GLF transport and periodic boundaries, FP64 state.
+// GLF transport and periodic boundaries.  The forward state is FP64 or the
+// mixed form's (FP32 N and F, FP64 gas); tapes and adjoint variables are
+// FP64 in both, so the mixed form's gradient is that of its own forward map,
+// evaluated at its FP32 radiation states.
 //
 // Forward step:  U_k --inject--> U_a --transport--> U_b --chemistry--> U_k+1
 // with parameters ln Ndot_s (sources) and ln n_H (cells).
@@ -272,14 +275,16 @@ __device__ __forceinline__ void dsubstep(const KChem &k, double h, const D &N, c
 // is the state after the chemistry with slot 6 = number of substeps taken.
 constexpr int TV = 7;
 
-// Thermochemistry of every cell as in rt_thermochem (FP64, one group,
-// hydrogen only), in place, writing the trace.  A cell that takes more
+// Thermochemistry of every cell as in rt_thermochem (one group, hydrogen
+// only, FP64 arithmetic on N and F stored as R), in place, writing the
+// trace.  A cell that takes more
 // substeps than counts[i], or whose entries would pass cap, sets flag bit
 // RT_TRACE_FLAG and records what fits.
 constexpr unsigned RT_TRACE_FLAG = 16u;
 
+template <typename R>
 __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ kp, size_t nc, double dt,
-                                                     double *__restrict__ N, double *__restrict__ F,
+                                                     R *__restrict__ N, R *__restrict__ F,
                                                      double *__restrict__ xHII, double *__restrict__ T,
                                                      const double *__restrict__ nH, const int32_t *__restrict__ counts,
                                                      const int64_t *__restrict__ off, long long cap,
@@ -293,10 +298,10 @@ __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ k
     const bool fits = cnt >= 0 && o + cnt < (int64_t)cap;
     double *tr = trace + (size_t)TV * (size_t)o;
     CS s;
-    s.N[0] = N[i];
+    s.N[0] = (double)N[i];
     s.N[1] = s.N[2] = 0.0;
     s.fs[1] = s.fs[2] = 1.0;
-    const double F0[3] = {F[i], F[nc + i], F[2 * nc + i]};
+    const double F0[3] = {(double)F[i], (double)F[nc + i], (double)F[2 * nc + i]};
     s.x = xHII[i];
     s.y2 = 0.0;
     s.y3 = 0.0;
@@ -339,10 +344,10 @@ __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ k
     }
     if (ok) {
         const double Tout = chem_finish<CM>(k, cc, s, fl);
-        N[i] = s.N[0];
-        F[i] = F0[0] * s.fs[0];
-        F[nc + i] = F0[1] * s.fs[0];
-        F[2 * nc + i] = F0[2] * s.fs[0];
+        N[i] = (R)s.N[0];
+        F[i] = (R)(F0[0] * s.fs[0]);
+        F[nc + i] = (R)(F0[1] * s.fs[0]);
+        F[2 * nc + i] = (R)(F0[2] * s.fs[0]);
         xHII[i] = s.x;
         T[i] = Tout;
     } else {
@@ -356,8 +361,9 @@ __global__ __launch_bounds__(256) void k_chem_record(const KChem *__restrict__ k
 // without the 10% checks.  The result is a smooth function of the inputs
 // whose derivative is the one the adjoint computes; with the recorded
 // inputs it reproduces the recorded step up to rounding.
-__global__ __launch_bounds__(256) void k_chem_replay(const KChem *__restrict__ kp, size_t nc, double *__restrict__ N,
-                                                     double *__restrict__ F, double *__restrict__ xHII,
+template <typename R>
+__global__ __launch_bounds__(256) void k_chem_replay(const KChem *__restrict__ kp, size_t nc, R *__restrict__ N,
+                                                     R *__restrict__ F, double *__restrict__ xHII,
                                                      double *__restrict__ T, const double *__restrict__ nH,
                                                      const int32_t *__restrict__ counts,
                                                      const int64_t *__restrict__ off, long long cap,
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(256) void k_chem_replay(const KChem *__restrict__ k
     const double nf = tr[TV * cnt + 6];
     const int n = (nf >= 0.0 && nf <= (double)cnt) ? (int)nf : 0;
     const bool iso = k.isothermal != 0;
-    double Nc = N[i], Fx = F[i], Fy = F[nc + i], Fz = F[2 * nc + i], x = xHII[i];
+    double Nc = (double)N[i], Fx = (double)F[i], Fy = (double)F[nc + i], Fz = (double)F[2 * nc + i], x = xHII[i];
     const double T0 = T[i];
     double Tm = iso ? T0 : T0 * (k.X * (1.0 + x));  // T_mu = T / mu
     const double lnnH = log(nH[i]);
@@ -387,10 +393,10 @@ __global__ __launch_bounds__(256) void k_chem_replay(const KChem *__restrict__ k
         x = xn;
         Tm = Tmn;
     }
-    N[i] = Nc;
-    F[i] = Fx;
-    F[nc + i] = Fy;
-    F[2 * nc + i] = Fz;
+    N[i] = (R)Nc;
+    F[i] = (R)Fx;
+    F[nc + i] = (R)Fy;
+    F[2 * nc + i] = (R)Fz;
     xHII[i] = x;
     T[i] = iso ? T0 : Tm / (k.X * (1.0 + x));
 }
@@ -632,21 +638,49 @@ hipError_t launch_offsets(const int32_t *counts, size_t nc, int64_t *off, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_chem_record(const KChem *dk, size_t nc, double dt, double *N, double *F, double *xHII, double *T,
+template <typename R>
+hipError_t launch_chem_record(const KChem *dk, size_t nc, double dt, R *N, R *F, double *xHII, double *T,
                               const double *nH, const int32_t *counts, const int64_t *off, long long cap,
                               double *trace, DevStats *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_chem_record, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, dk, nc, dt, N, F, xHII, T,
-                       nH, counts, off, cap, trace, st);
+    hipLaunchKernelGGL(k_chem_record<R>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, dk, nc, dt, N, F, xHII,
+                       T, nH, counts, off, cap, trace, st);
     return hipGetLastError();
 }
+template hipError_t launch_chem_record<double>(const KChem *, size_t, double, double *, double *, double *, double *,
+                                               const double *, const int32_t *, const int64_t *, long long, double *,
+                                               DevStats *, hipStream_t);
+template hipError_t launch_chem_record<float>(const KChem *, size_t, double, float *, float *, double *, double *,
+                                              const double *, const int32_t *, const int64_t *, long long, double *,
+                                              DevStats *, hipStream_t);
 
-hipError_t launch_chem_replay(const KChem *dk, size_t nc, double *N, double *F, double *xHII, double *T,
-                              const double *nH, const int32_t *counts, const int64_t *off, long long cap,
-                              const double *trace, hipStream_t s)
+template <typename R>
+hipError_t launch_chem_replay(const KChem *dk, size_t nc, R *N, R *F, double *xHII, double *T, const double *nH,
+                              const int32_t *counts, const int64_t *off, long long cap, const double *trace,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_chem_replay, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, dk, nc, N, F, xHII, T, nH,
-                       counts, off, cap, trace);
+    hipLaunchKernelGGL(k_chem_replay<R>, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, dk, nc, N, F, xHII, T,
+                       nH, counts, off, cap, trace);
+    return hipGetLastError();
+}
+template hipError_t launch_chem_replay<double>(const KChem *, size_t, double *, double *, double *, double *,
+                                               const double *, const int32_t *, const int64_t *, long long,
+                                               const double *, hipStream_t);
+template hipError_t launch_chem_replay<float>(const KChem *, size_t, float *, float *, double *, double *,
+                                              const double *, const int32_t *, const int64_t *, long long,
+                                              const double *, hipStream_t);
+
+// the pre-transport radiation of a step, widened to the tape's FP64
+__global__ void k_widen(const float *__restrict__ a, double *__restrict__ b, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
+}
+
+hipError_t launch_widen(const float *a, double *b, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
     return hipGetLastError();
 }
 

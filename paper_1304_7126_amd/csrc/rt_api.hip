@@ -39,7 +39,6 @@ struct rt_ctx {
     // smoothed RT: source index per cell, each source cell's N before the
     // injection, and where the step stands (0: nothing yet, 1: injected,
     // 2: transported; injected says whether 1 preceded 2)
-    int32_t *src_map = nullptr;
     double *src_prev = nullptr;
     int sm_phase = 0;
     bool sm_injected = false;
@@ -67,12 +66,12 @@ struct rt_ctx {
     };
     std::vector<Pend> pend;
     std::vector<hipEvent_t> pool;
-    double t_ms[5] = {0, 0, 0, 0, 0};
-    long long t_n[5] = {0, 0, 0, 0, 0};
+    double t_ms[RT_TIMING_CLASSES] = {};
+    long long t_n[RT_TIMING_CLASSES] = {};
     std::string err;
 };
 
-enum { TM_INJECT = 0, TM_TRANSPORT = 1, TM_HEAD = 2, TM_TAIL = 3, TM_OTHER = 4 };
+enum { TM_INJECT = 0, TM_TRANSPORT = 1, TM_HEAD = 2, TM_TAIL = 3, TM_OTHER = 4, TM_ACCT = 5 };
 
 static hipEvent_t ev_take(rt_ctx *c)
 {
@@ -463,11 +462,6 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
     if (e == hipSuccess) e = hipMalloc((void **)&c->dred, sizeof(RedOut));
     if (e == hipSuccess) e = hipMalloc((void **)&c->dkchem, sizeof(KChem));
     if (e == hipSuccess) e = hipMemcpy(c->dkchem, &c->kchem, sizeof(KChem), hipMemcpyHostToDevice);
-    if (e == hipSuccess && params->smooth) {
-        e = hipMalloc((void **)&c->src_map, c->grid.ncell * sizeof(int32_t));
-        if (e == hipSuccess) e = launch_source_map(c->src_map, c->grid.ncell, nullptr, 0, nullptr);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
-    }
     if (e != hipSuccess) {
         g_init_err = std::string("device table allocation failed: ") + hipGetErrorString(e);
         rt_free(c);
@@ -488,6 +482,12 @@ extern "C" rt_status rt_init(const rt_grid *grid, const rt_groups *groups, const
 // per-cell attempt counts of the previous chemistry pass (one byte per cell)
 static size_t prev_att_bytes(const rt_ctx *c) { return (c->grid.ncell + 255) & ~(size_t)255; }
 
+// smoothed RT: the source index of every cell (int32, -1: none)
+static size_t src_map_bytes(const rt_ctx *c)
+{
+    return c->params.smooth ? (c->grid.ncell * sizeof(int32_t) + 255) & ~(size_t)255 : 0;
+}
+
 // accounting partials: 6 doubles per block of either transport kernel
 static size_t acct_region(const rt_ctx *c)
 {
@@ -499,7 +499,7 @@ static size_t acct_region(const rt_ctx *c)
 static size_t scratch_need(const rt_ctx *c)
 {
     return ((reduction_scratch_bytes() + 255) & ~(size_t)255) + queue_bytes(c->qcap_max, c->params.smooth != 0) +
-           acct_region(c) + prev_att_bytes(c);
+           acct_region(c) + prev_att_bytes(c) + src_map_bytes(c);
 }
 
 // accounting partials: after the reduction partials and the queue
@@ -511,6 +511,21 @@ static double *acct_part(const rt_ctx *c)
 
 // previous-pass attempt counts: after the accounting partials
 static uint8_t *prev_att(const rt_ctx *c) { return (uint8_t *)acct_part(c) + acct_region(c); }
+
+// the source map (smoothed RT): after the attempt counts, null without scratch
+static int32_t *src_map(const rt_ctx *c)
+{
+    if (!c->params.smooth || !c->st.scratch) return nullptr;
+    return (int32_t *)(prev_att(c) + prev_att_bytes(c));
+}
+
+// write the source map of the current sources (smoothed RT, scratch bound)
+static hipError_t rebuild_src_map(rt_ctx *c)
+{
+    int32_t *map = src_map(c);
+    if (!map) return hipSuccess;
+    return launch_source_map(map, c->grid.ncell, c->src_cell, c->nsrc, c->stream);
+}
 
 // whether the transport runs as the z-marching kernel (else per cell)
 static bool use_zmarch(const rt_ctx *c)
@@ -540,6 +555,7 @@ extern "C" rt_status rt_bind(rt_ctx *c, const rt_state *s)
     c->sm_phase = 0;
     // no previous pass yet: every count starts at zero
     if (c->st.scratch) RT_HIP(c, hipMemset(prev_att(c), 0, c->grid.ncell));
+    RT_HIP(c, rebuild_src_map(c));
     return RT_OK;
 }
 
@@ -599,8 +615,10 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     c->nsrc_in = 0;
     c->src_rate_host.clear();
     c->sm_phase = 0;
-    if (c->src_map) RT_HIP(c, launch_source_map(c->src_map, c->grid.ncell, nullptr, 0, c->stream));
-    if (cells.empty()) return RT_OK;
+    if (cells.empty()) {
+        RT_HIP(c, rebuild_src_map(c));
+        return RT_OK;
+    }
     {
         std::vector<int32_t> in_cell(n);
         std::vector<double> in_rate(n);
@@ -621,10 +639,8 @@ extern "C" rt_status rt_set_sources(rt_ctx *c, int n, const int32_t *ijk, const 
     RT_HIP(c, hipMemcpy(c->src_rate, rates.data(), rates.size() * sizeof(double), hipMemcpyHostToDevice));
     c->nsrc = (int)cells.size();
     c->src_rate_host = rates;
-    if (c->src_map) {
-        RT_HIP(c, hipMalloc((void **)&c->src_prev, rates.size() * sizeof(double)));
-        RT_HIP(c, launch_source_map(c->src_map, c->grid.ncell, c->src_cell, c->nsrc, c->stream));
-    }
+    if (c->params.smooth) RT_HIP(c, hipMalloc((void **)&c->src_prev, rates.size() * sizeof(double)));
+    RT_HIP(c, rebuild_src_map(c));
     return RT_OK;
 }
 
@@ -737,13 +753,15 @@ static rt_status do_transport(rt_ctx *c, double dt)
     return RT_OK;
 }
 
-// photon totals of the current radiation set into dred
+// photon totals of the current radiation set: per-block partials in the
+// scratch's reduction area (the ledger sums them)
 static rt_status acct_reduce(rt_ctx *c)
 {
-    const double V = c->grid.dx * c->grid.dx * c->grid.dx;
-    RT_HIP(c, launch_reduce(c->fp32, c->grid.ncell, c->groups.M, c->groups.c_r, V, c->st.N[c->cur], c->st.F[c->cur],
-                            c->st.xHII, c->st.nH, c->st.scratch, c->dred, c->stream));
-    return RT_OK;
+    return timed(c, TM_ACCT, [&]() -> rt_status {
+        RT_HIP(c, launch_sum_n(c->fp32, c->grid.ncell, c->groups.M, c->st.N[c->cur], (double *)c->st.scratch,
+                               c->stream));
+        return RT_OK;
+    });
 }
 
 // close the step's ledger after the chemistry
@@ -752,10 +770,14 @@ static rt_status acct_close(rt_ctx *c, double dt)
     const double V = c->grid.dx * c->grid.dx * c->grid.dx;
     rt_status r = acct_reduce(c);
     if (r != RT_OK) return r;
-    RT_HIP(c, launch_ledger(c->acct_pending ? 2 : 1, acct_part(c), c->acct_nblk, c->groups.M, V,
-                            dt / (c->a_cosmo * c->a_cosmo) * c->grid.dx * c->grid.dx, c->dred, c->dstats, c->stream));
+    r = timed(c, TM_ACCT, [&]() -> rt_status {
+        RT_HIP(c, launch_ledger(c->acct_pending ? 2 : 1, acct_part(c), c->acct_nblk, (const double *)c->st.scratch,
+                                c->groups.M, V, dt / (c->a_cosmo * c->a_cosmo) * c->grid.dx * c->grid.dx, c->dstats,
+                                c->stream));
+        return RT_OK;
+    });
     c->acct_pending = false;
-    return RT_OK;
+    return r;
 }
 
 // smoothed RT: the radiation set before the step and the source table
@@ -764,7 +786,7 @@ static SmoothArgs smooth_args(const rt_ctx *c, int pre_set, bool injected)
     SmoothArgs a;
     a.N = c->st.N[pre_set];
     a.F = c->st.F[pre_set];
-    a.map = injected ? c->src_map : nullptr;
+    a.map = injected ? src_map(c) : nullptr;
     a.prev = c->src_prev;
     return a;
 }
@@ -783,7 +805,13 @@ static rt_status do_chem(rt_ctx *c, double dt)
         // no transport before this chemistry: its input totals come from a reduction
         rt_status r = acct_reduce(c);
         if (r != RT_OK) return r;
-        RT_HIP(c, launch_ledger(0, nullptr, 0, c->groups.M, 0.0, 0.0, c->dred, c->dstats, c->stream));
+        const double V = c->grid.dx * c->grid.dx * c->grid.dx;
+        r = timed(c, TM_ACCT, [&]() -> rt_status {
+            RT_HIP(c, launch_ledger(0, nullptr, 0, (const double *)c->st.scratch, c->groups.M, V, 0.0, c->dstats,
+                                    c->stream));
+            return RT_OK;
+        });
+        if (r != RT_OK) return r;
     }
     unsigned long long *hist = c->acct ? c->dstats->hist : nullptr;
     for (int part = 1; part <= 2; ++part) {
@@ -1029,7 +1057,7 @@ extern "C" rt_status rt_get_timing(rt_ctx *c, rt_timing *out)
 {
     if (!c || !out) return RT_EINVAL;
     fold_timing(c);
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < RT_TIMING_CLASSES; ++k) {
         out->ms[k] = c->t_ms[k];
         out->launches[k] = c->t_n[k];
         c->t_ms[k] = 0.0;
@@ -1048,7 +1076,6 @@ static rt_status adj_supported(rt_ctx *c, double dt)
     if (c->groups.M != 1) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs one photon group (M = %d)", c->groups.M);
     if (c->params.Y != 0.0) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs hydrogen-only gas (Y = 0)");
     if (c->params.flux != RT_FLUX_GLF) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the GLF flux");
-    if (c->fp32) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs RT_PREC_FP64");
     if (c->params.smooth) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs smooth = 0");
     if (!c->params.otsa) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs the on-the-spot approximation (otsa = 1)");
     if (c->a_cosmo != 1.0) RT_FAIL(c, RT_EUNSUPPORTED, "the adjoint needs a static box (expansion factor 1)");
@@ -1092,13 +1119,24 @@ extern "C" rt_status rt_step_record(rt_ctx *c, double dt, const rt_tape *t)
     const size_t nc = c->grid.ncell;
     RT_HIP(c, launch_offsets(t->counts, nc, t->off, c->stream));
     if ((r = do_inject(c, dt)) != RT_OK) return r;
-    RT_HIP(c, hipMemcpyAsync(t->Na, c->st.N[c->cur], nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    RT_HIP(c, hipMemcpyAsync(t->Fa, c->st.F[c->cur], 3 * nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (c->fp32) {
+        RT_HIP(c, launch_widen((const float *)c->st.N[c->cur], t->Na, nc, c->stream));
+        RT_HIP(c, launch_widen((const float *)c->st.F[c->cur], t->Fa, 3 * nc, c->stream));
+    } else {
+        RT_HIP(c, hipMemcpyAsync(t->Na, c->st.N[c->cur], nc * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        RT_HIP(c, hipMemcpyAsync(t->Fa, c->st.F[c->cur], 3 * nc * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+    }
     if ((r = do_transport(c, dt)) != RT_OK) return r;
     return timed(c, TM_OTHER, [&]() -> rt_status {
-        RT_HIP(c, launch_chem_record(c->dkchem, nc, dt, (double *)c->st.N[c->cur], (double *)c->st.F[c->cur],
-                                     c->st.xHII, c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace, c->dstats,
-                                     c->stream));
+        if (c->fp32)
+            RT_HIP(c, launch_chem_record(c->dkchem, nc, dt, (float *)c->st.N[c->cur], (float *)c->st.F[c->cur],
+                                         c->st.xHII, c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace,
+                                         c->dstats, c->stream));
+        else
+            RT_HIP(c, launch_chem_record(c->dkchem, nc, dt, (double *)c->st.N[c->cur], (double *)c->st.F[c->cur],
+                                         c->st.xHII, c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace,
+                                         c->dstats, c->stream));
         return RT_OK;
     });
 }
@@ -1114,8 +1152,14 @@ extern "C" rt_status rt_step_replay(rt_ctx *c, double dt, const rt_tape *t)
     if ((r = do_inject(c, dt)) != RT_OK) return r;
     if ((r = do_transport(c, dt)) != RT_OK) return r;
     return timed(c, TM_OTHER, [&]() -> rt_status {
-        RT_HIP(c, launch_chem_replay(c->dkchem, nc, (double *)c->st.N[c->cur], (double *)c->st.F[c->cur], c->st.xHII,
-                                     c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace, c->stream));
+        if (c->fp32)
+            RT_HIP(c, launch_chem_replay(c->dkchem, nc, (float *)c->st.N[c->cur], (float *)c->st.F[c->cur],
+                                         c->st.xHII, c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace,
+                                         c->stream));
+        else
+            RT_HIP(c, launch_chem_replay(c->dkchem, nc, (double *)c->st.N[c->cur], (double *)c->st.F[c->cur],
+                                         c->st.xHII, c->st.T, c->st.nH, t->counts, t->off, t->cap, t->trace,
+                                         c->stream));
         return RT_OK;
     });
 }
@@ -1160,7 +1204,6 @@ extern "C" void rt_free(rt_ctx *c)
     if (c->src_rate) (void)hipFree(c->src_rate);
     if (c->src_in_cell) (void)hipFree(c->src_in_cell);
     if (c->src_in_rate) (void)hipFree(c->src_in_rate);
-    if (c->src_map) (void)hipFree(c->src_map);
     if (c->src_prev) (void)hipFree(c->src_prev);
     if (c->dstats) (void)hipFree(c->dstats);
     if (c->dred) (void)hipFree(c->dred);

@@ -718,13 +718,27 @@ static rt_status enqueue_step(rt_batch *b, double dt, int src)
     return RT_OK;
 }
 
+// the largest step every box's transport allows: the finest box's dx over 3 c_r
+static double batch_dt_limit(const rt_batch *b)
+{
+    double dxmin = b->dx[0];
+    for (double v : b->dx) dxmin = v < dxmin ? v : dxmin;
+    return dxmin / (3.0 * b->c_r);
+}
+
+extern "C" rt_status rt_batch_courant_dt(const rt_batch *b, double courant, double *dt)
+{
+    if (!b || !dt || !(courant > 0)) return RT_EINVAL;
+    *dt = courant * batch_dt_limit(b);
+    return RT_OK;
+}
+
 extern "C" rt_status rt_batch_step(rt_batch *b, double dt, int nsteps)
 {
     if (!b) return RT_EINVAL;
     if (!b->bound) BT_FAIL(b, RT_ESTATE, "no state bound");
     if (nsteps < 0) BT_FAIL(b, RT_EINVAL, "nsteps < 0");
-    double dxmin = b->dx[0];
-    for (double v : b->dx) dxmin = v < dxmin ? v : dxmin;
+    const double dxmin = batch_dt_limit(b) * 3.0 * b->c_r;
     if (!(dt > 0)) dt = 0.8 * dxmin / (3.0 * b->c_r);
     if (dt > dxmin / (3.0 * b->c_r) * (1.0 + 1e-12))
         BT_FAIL(b, RT_EINVAL, "dt = %g exceeds the Courant limit of the finest box", dt);

@@ -102,12 +102,16 @@ hipError_t launch_transport_z(bool fp32, int flux, const KGrid &g, int M, double
                               const void *Fin, void *Nout, void *Fout, const void *hll, int nf, int nth, double *acct,
                               hipStream_t s);
 
+// per-block sums of N of each group of a radiation set: RED_BLOCKS x 3
+// doubles at part (launch_ledger reads them)
+hipError_t launch_sum_n(bool fp32, size_t ncell, int M, const void *N, double *part, hipStream_t s);
+
 // mode 0: record the current photon totals as the pre-chemistry totals;
 // mode 1: absorbed += pre-chemistry totals - current totals;
 // mode 2: as 1 with the pre-chemistry totals and the outflow taken from the
-// transport partials.  red holds the current totals (launch_reduce).
-hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, int M, double V, double dtdx2,
-                         const RedOut *red, DevStats *st, hipStream_t s);
+// transport partials.  npart: launch_sum_n partials of the current set.
+hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, const double *npart, int M, double V,
+                         double dtdx2, DevStats *st, hipStream_t s);
 
 // queue of cells still subcycling after the head pass (caller scratch), in
 // three regions the tail works off in order: cells that took many attempts
@@ -193,12 +197,15 @@ inline void kchem_derive(KChem &k)
 // differentiation form (rt_adjoint.hip)
 size_t adj_scan_parts(size_t nc);
 hipError_t launch_offsets(const int32_t *counts, size_t nc, int64_t *off, hipStream_t s);
-hipError_t launch_chem_record(const KChem *dk, size_t nc, double dt, double *N, double *F, double *xHII, double *T,
+template <typename R>
+hipError_t launch_chem_record(const KChem *dk, size_t nc, double dt, R *N, R *F, double *xHII, double *T,
                               const double *nH, const int32_t *counts, const int64_t *off, long long cap,
                               double *trace, DevStats *st, hipStream_t s);
-hipError_t launch_chem_replay(const KChem *dk, size_t nc, double *N, double *F, double *xHII, double *T,
-                              const double *nH, const int32_t *counts, const int64_t *off, long long cap,
-                              const double *trace, hipStream_t s);
+template <typename R>
+hipError_t launch_chem_replay(const KChem *dk, size_t nc, R *N, R *F, double *xHII, double *T, const double *nH,
+                              const int32_t *counts, const int64_t *off, long long cap, const double *trace,
+                              hipStream_t s);
+hipError_t launch_widen(const float *a, double *b, size_t n, hipStream_t s);
 hipError_t launch_chem_adj(const KChem *dk, size_t nc, const double *nH, const int32_t *counts, const int64_t *off,
                            long long cap, const double *trace, const double *lN, const double *lF, double *lx,
                            double *lT, double *wN, double *wF, double *g, hipStream_t s);

@@ -584,6 +584,36 @@ QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap)
     return q;
 }
 
+// Sum over the 64 lanes of a wavefront by butterfly exchanges: every lane
+// ends with the same total, combined in the same order on every run.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Diagnostics of a state (rt_get_stats): per block, grid-stride over the
+// cells in a fixed order, then wave butterflies and the block's four waves
+// in order.
 template <typename R>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(size_t nc, int M, double c, double V,
                                                                 const R *__restrict__ N, const R *__restrict__ F,
@@ -607,83 +637,145 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(size_t nc, int M
         }
         ion += xHII[i] * nH[i];
     }
-    __shared__ double s[6][RED_THREADS];
-    const int t = threadIdx.x;
-    s[0][t] = ph[0];
-    s[1][t] = ph[1];
-    s[2][t] = ph[2];
-    s[3][t] = ion;
-    s[4][t] = mf;
-    s[5][t] = mn;
+    __shared__ double s[RED_THREADS / 64][6];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double v[6] = {wave_sum(ph[0]), wave_sum(ph[1]), wave_sum(ph[2]), wave_sum(ion), wave_max(mf),
+                         wave_min(mn)};
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s[w][q] = v[q];
     __syncthreads();
-    for (int o = RED_THREADS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x == 0) {
+        double a[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) a[q] = s[0][q];
+        for (int k = 1; k < RED_THREADS / 64; ++k) {
+            for (int q = 0; q < 4; ++q) a[q] += s[k][q];
+            a[4] = s[k][4] > a[4] ? s[k][4] : a[4];
+            a[5] = s[k][5] < a[5] ? s[k][5] : a[5];
+        }
+        RedOut r;
+        for (int g = 0; g < 3; ++g) r.photons[g] = a[g] * V;
+        r.ionised = a[3] * V;
+        r.maxf = a[4];
+        r.minN = a[5];
+        part[blockIdx.x] = r;
+    }
+}
+
+// The block partials in a fixed order: each of 256 threads combines the
+// partials t, t + 256, ... in turn, then a tree over the threads.
+__global__ __launch_bounds__(256) void k_reduce_final(const RedOut *__restrict__ part, int np, RedOut *__restrict__ out)
+{
+    __shared__ double s[6][256];
+    const int t = threadIdx.x;
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 1e300};
+    for (int b = t; b < np; b += 256) {
+        const RedOut &r = part[b];
+        for (int g = 0; g < 3; ++g) a[g] += r.photons[g];
+        a[3] += r.ionised;
+        a[4] = r.maxf > a[4] ? r.maxf : a[4];
+        a[5] = r.minN < a[5] ? r.minN : a[5];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) s[q][t] = a[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
         if (t < o) {
             for (int q = 0; q < 4; ++q) s[q][t] += s[q][t + o];
-            s[4][t] = s[4][t] > s[4][t + o] ? s[4][t] : s[4][t + o];
-            s[5][t] = s[5][t] < s[5][t + o] ? s[5][t] : s[5][t + o];
+            s[4][t] = s[4][t + o] > s[4][t] ? s[4][t + o] : s[4][t];
+            s[5][t] = s[5][t + o] < s[5][t] ? s[5][t + o] : s[5][t];
         }
         __syncthreads();
     }
     if (t == 0) {
         RedOut r;
-        for (int g = 0; g < 3; ++g) r.photons[g] = s[g][0] * V;
-        r.ionised = s[3][0] * V;
+        for (int g = 0; g < 3; ++g) r.photons[g] = s[g][0];
+        r.ionised = s[3][0];
         r.maxf = s[4][0];
         r.minN = s[5][0];
-        part[blockIdx.x] = r;
+        *out = r;
     }
 }
 
-__global__ void k_reduce_final(const RedOut *__restrict__ part, int np, RedOut *__restrict__ out)
+// Photons per group of one radiation set, for the step's ledger: per block
+// the sum of N of each group (grid-stride in a fixed order, wave
+// butterflies, the four waves in order) at part[3 b + g].
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_sum_n(size_t nc, int M, const R *__restrict__ N,
+                                                       double *__restrict__ part)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    RedOut r = part[0];
-    for (int b = 1; b < np; ++b) {
-        for (int g = 0; g < 3; ++g) r.photons[g] += part[b].photons[g];
-        r.ionised += part[b].ionised;
-        r.maxf = part[b].maxf > r.maxf ? part[b].maxf : r.maxf;
-        r.minN = part[b].minN < r.minN ? part[b].minN : r.minN;
+    double sg[3] = {0.0, 0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (size_t)gridDim.x * blockDim.x)
+        for (int g = 0; g < M; ++g) sg[g] += (double)N[(size_t)g * nc + i];
+    __shared__ double s[RED_THREADS / 64][3];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        const double v = wave_sum(sg[g]);
+        if (lane == 0) s[w][g] = v;
     }
-    *out = r;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double a = s[0][threadIdx.x];
+        for (int k = 1; k < RED_THREADS / 64; ++k) a += s[k][threadIdx.x];
+        part[(size_t)3 * blockIdx.x + threadIdx.x] = a;
+    }
 }
 
-// Photon ledger of one step (fixed-order sums; see launch_ledger).
-__global__ __launch_bounds__(256) void k_ledger(int mode, const double *__restrict__ acct, unsigned nblk, int M,
-                                                double V, double dtdx2, const RedOut *__restrict__ red,
+hipError_t launch_sum_n(bool fp32, size_t ncell, int M, const void *N, double *part, hipStream_t s)
+{
+    if (fp32)
+        hipLaunchKernelGGL(k_sum_n<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, ncell, M, (const float *)N, part);
+    else
+        hipLaunchKernelGGL(k_sum_n<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, ncell, M, (const double *)N,
+                           part);
+    return hipGetLastError();
+}
+
+// Photon ledger of one step (fixed-order sums; see launch_ledger): the
+// photons of the current set from the k_sum_n partials, and with mode 2 the
+// transported photons and the boundary outflow from the transport partials.
+__global__ __launch_bounds__(256) void k_ledger(int mode, const double *__restrict__ acct, unsigned nblk,
+                                                const double *__restrict__ npart, int M, double V, double dtdx2,
                                                 DevStats *__restrict__ st)
 {
-    __shared__ double sh[6][256];
+    __shared__ double sh[9][256];
     const int t = threadIdx.x;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (mode == 2)
         for (unsigned b = t; b < nblk; b += 256)
 #pragma unroll
             for (int q = 0; q < 6; ++q) v[q] += acct[(size_t)6 * b + q];
+    for (unsigned b = t; b < (unsigned)RED_BLOCKS; b += 256)
 #pragma unroll
-    for (int q = 0; q < 6; ++q) sh[q][t] = v[q];
+        for (int g = 0; g < 3; ++g) v[6 + g] += npart[(size_t)3 * b + g];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sh[q][t] = v[q];
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (t < o)
 #pragma unroll
-            for (int q = 0; q < 6; ++q) sh[q][t] += sh[q][t + o];
+            for (int q = 0; q < 9; ++q) sh[q][t] += sh[q][t + o];
         __syncthreads();
     }
     if (t != 0) return;
     for (int g = 0; g < M; ++g) {
+        const double now = sh[6 + g][0] * V;
         if (mode == 0) {
-            st->Tpre[g] = red->photons[g];
+            st->Tpre[g] = now;
             continue;
         }
         const double T0 = mode == 2 ? sh[g][0] * V : st->Tpre[g];
-        st->absorbed[g] += T0 - red->photons[g];
+        st->absorbed[g] += T0 - now;
         if (mode == 2) st->outflow[g] += sh[3 + g][0] * dtdx2;
     }
 }
 
-hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, int M, double V, double dtdx2,
-                         const RedOut *red, DevStats *st, hipStream_t s)
+hipError_t launch_ledger(int mode, const double *acct, unsigned nblk, const double *npart, int M, double V,
+                         double dtdx2, DevStats *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ledger, dim3(1), dim3(256), 0, s, mode, acct, nblk, M, V, dtdx2, red, st);
+    hipLaunchKernelGGL(k_ledger, dim3(1), dim3(256), 0, s, mode, acct, nblk, npart, M, V, dtdx2, st);
     return hipGetLastError();
 }
 
@@ -697,7 +789,7 @@ hipError_t launch_reduce(bool fp32, size_t ncell, int M, double c, double V, con
     else
         hipLaunchKernelGGL(k_reduce_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, ncell, M, c, V,
                            (const double *)N, (const double *)F, xHII, nH, part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, part, RED_BLOCKS, dev_out);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, part, RED_BLOCKS, dev_out);
     return hipGetLastError();
 }
 

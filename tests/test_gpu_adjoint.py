@@ -8,7 +8,12 @@ behind torch.autograd.Function, with checkpointing).
     with several checkpoint segments, isothermal and with T evolving;
   - on the full differentiation workload (64^3, 16 sources, 300 steps,
     checkpoints every 20 steps) they equal central finite differences
-    (h = 1e-6, FP64) of the GPU forward run.
+    (h = 1e-6, FP64) of the GPU forward run;
+  - the mixed form's gradient (FP32 radiation in the forward steps) stays
+    close to the FP64 one on that workload;
+  - a backward uses the parameters of its own forward run, whatever the
+    context holds by then, and refuses once a later forward run has
+    replaced the checkpoints.
 """
 import numpy as np
 import pytest
@@ -21,10 +26,10 @@ from oracle import physics
 pytestmark = pytest.mark.gpu
 
 
-def make_run(w, every):
+def make_run(w, every, fp32=False):
     from paper_1304_7126_amd import RTContext
     from paper_1304_7126_amd.adjoint import GradientRun
-    ctx = RTContext.for_workload(w, counters=True)
+    ctx = RTContext.for_workload(w, counters=True, fp32=fp32)
     ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
     dt = ctx.courant_dt()
     run = GradientRun(ctx, ijk, dt, w.steps, x0=w.xHII0, T0=w.T0, every=every)
@@ -38,11 +43,12 @@ def params(w, nd):
     return st, lnnd, lnnH
 
 
-def test_recorded_steps_equal_rt_step():
+@pytest.mark.parametrize("fp32", [False, True])
+def test_recorded_steps_equal_rt_step(fp32):
     assert torch.cuda.is_available()
     from paper_1304_7126_amd import capi
     w = ri.grey_box(20, 3.3 * 20 / 64, 6, 12, seed=3)
-    run, ijk, nd, dt = make_run(w, every=5)
+    run, ijk, nd, dt = make_run(w, every=5, fp32=fp32)
     st, lnnd, lnnH = params(w, nd)
     x_fwd = run.forward(lnnd, lnnH)
     ctx = run.ctx
@@ -187,3 +193,80 @@ def test_gradient_equals_gpu_central_differences_at_full_size():
     print(f"L = {L0:.6e}; {flipped} of {len(dirs)} free-running pairs changed the substep schedule", flush=True)
     assert not bad_frozen, bad_frozen
     assert not bad_free, bad_free
+
+
+def test_backward_uses_the_parameters_of_its_forward():
+    assert torch.cuda.is_available()
+    from paper_1304_7126_amd import capi
+    from paper_1304_7126_amd.adjoint import rt_run
+    w = ri.grey_box(12, 3.3 * 12 / 64, 4, 10, seed=5)
+    run, ijk, nd, dt = make_run(w, every=4)
+    st, lnnd, lnnH = params(w, nd)
+    target = torch.full_like(lnnH, 0.5)
+    with torch.no_grad():
+        x = run.forward(lnnd, lnnH)
+        g_ref = [t.clone() for t in run.backward(2.0 * (x - target))[:2]]
+    a = lnnd.clone().requires_grad_(True)
+    b = lnnH.clone().requires_grad_(True)
+    loss = ((rt_run(run, a, b) - target) ** 2).sum()
+    # something else puts other sources and densities on the context
+    # (a finite-difference probe, say) before the backward
+    run._set_params(lnnd + 0.3, lnnH - 0.2)
+    loss.backward()
+    assert torch.equal(a.grad, g_ref[0].cpu()) and torch.equal(b.grad, g_ref[1])
+    # a later forward run replaces the checkpoints: the earlier graph refuses
+    a1 = lnnd.clone().requires_grad_(True)
+    b1 = lnnH.clone().requires_grad_(True)
+    l1 = ((rt_run(run, a1, b1) - target) ** 2).sum()
+    with torch.no_grad():
+        run.forward(lnnd + 0.1, lnnH)
+    with pytest.raises(capi.RTError):
+        l1.backward()
+
+
+def test_mixed_gradient_close_to_fp64_at_full_size():
+    """C5's workload (64^3, 16 sources, 300 steps, checkpoints every 20)
+    differentiated twice: in FP64 and in the mixed form.  The loss uses the
+    FP64 target in both.  Compared: L, the 16 source gradients and the
+    directional derivatives along 4 random directions over all log
+    densities (relative to the FP64 values), and the per-cell density
+    gradient (global-normalised)."""
+    assert torch.cuda.is_available()
+    from paper_1304_7126_amd.adjoint import rt_run
+    w = ri.grey_64(steps=300, seed=0)
+    res = {}
+    target = None
+    for fp32 in (False, True):
+        run, ijk, nd, dt = make_run(w, every=20, fp32=fp32)
+        st, lnnd, lnnH = params(w, nd)
+        if target is None:
+            with torch.no_grad():
+                target = run.forward(torch.tensor(ri.perturbed_log_rates(nd, w.seed)), lnnH).clone()
+        a = lnnd.clone().requires_grad_(True)
+        b = lnnH.clone().requires_grad_(True)
+        L = ((rt_run(run, a, b) - target) ** 2).sum()
+        L.backward()
+        res[fp32] = (float(L.item()), a.grad.numpy().copy(), b.grad.cpu().numpy().copy(),
+                     run.last_backward["flags"])
+        run.ctx.close()
+        del run
+        torch.cuda.empty_cache()
+    (L64, gs64, gn64, f64), (L32, gs32, gn32, f32) = res[False], res[True]
+    assert f64 == 0 and f32 == 0
+    rng = np.random.default_rng(5)
+    dirs = [rng.standard_normal(gn64.shape) for _ in range(4)]
+    d64 = np.array([np.sum(gn64 * v) for v in dirs])
+    d32 = np.array([np.sum(gn32 * v) for v in dirs])
+    e_L = abs(L32 - L64) / abs(L64)
+    e_src = float(np.max(np.abs(gs32 - gs64)) / np.max(np.abs(gs64)))
+    e_src_each = float(np.max(np.abs(gs32 - gs64) / np.abs(gs64)))
+    e_dir = float(np.max(np.abs(d32 - d64) / np.abs(d64)))
+    e_cell = float(np.max(np.abs(gn32 - gn64)) / np.max(np.abs(gn64)))
+    sc = np.max(np.abs(gn64))
+    m = np.abs(gn64) > 1e-6 * sc
+    rel = np.abs(gn32[m] - gn64[m]) / np.abs(gn64[m])
+    print(f"mixed vs FP64 adjoint: L {e_L:.3e}, source gradients e_inf {e_src:.3e} (each {e_src_each:.3e}), "
+          f"density directions {e_dir:.3e}, density gradient e_inf {e_cell:.3e}, per-cell p50 "
+          f"{np.quantile(rel, 0.5):.3e} p99 {np.quantile(rel, 0.99):.3e} max {rel.max():.3e}", flush=True)
+    assert e_L <= 1e-3
+    assert e_src <= 1e-2 and e_dir <= 1e-2
