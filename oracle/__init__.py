@@ -57,6 +57,7 @@ def lib():
         L.or_courant_dt.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_courant_dt.restype = ctypes.c_double
         L.or_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_diagnostics.argtypes = [ctypes.POINTER(OrParams), dp, dp, dp, dp, dp]
         L.or_boundary_outflow.argtypes = [ctypes.POINTER(OrParams), ctypes.c_double, dp, dp, dp]
         lp = ctypes.POINTER(ctypes.c_longlong)
@@ -114,6 +115,11 @@ def rate(name: str, T: float, a_exp: float = 1.0):
 def threads() -> int:
     """Number of OpenMP threads the oracle runs with."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops with n threads."""
+    lib().or_set_threads(int(n))
 
 
 def _dp(a):

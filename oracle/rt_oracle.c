@@ -950,6 +950,16 @@ double or_courant_dt(double dx, double c_r, double courant)
     return courant * dx / (3.0 * c_r);
 }
 
+/* set the number of threads of the oracle's parallel loops */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* threads the oracle's parallel loops use */
 int or_threads(void)
 {

@@ -270,6 +270,22 @@ def lognormal_256(steps: int = 100, seed: int = 0) -> Workload:
     return lognormal_box(256, 13.2, 200, steps, seed)
 
 
+def subbox(w: Workload, n_sub: int):
+    """The cells [0, n_sub)^3 of workload w's realisation (density field and
+    the sources inside them) as a periodic box of its own, with the same cell
+    size: (workload, initial state, source cells (K,3), source rates (K,))."""
+    ws = dataclasses.replace(w, name=f"{w.name}_sub{n_sub}", n=(n_sub,) * 3, L=n_sub * w.dx,
+                             bc=(BC_PERIODIC,) * 6)
+    full = lognormal_nH(w.n, w.sigma_ln, w.nH_mean, w.seed) if w.sigma_ln > 0 else None
+    st = initial_state(ws)
+    if full is not None:
+        st["nH"] = np.ascontiguousarray(full[:n_sub, :n_sub, :n_sub])
+    ijk, nd = random_sources(w.n, w.n_sources, w.seed)
+    keep = np.all(ijk < n_sub, axis=1)
+    ws.n_sources = int(keep.sum())
+    return ws, st, np.ascontiguousarray(ijk[keep]), np.ascontiguousarray(nd[keep])
+
+
 def grey_box(n: int, L_kpc: float, n_sources: int, steps: int, seed: int = 0, isothermal: bool = False,
              sigma_ln: float = 0.8) -> Workload:
     """Periodic hydrogen-only box (X = 1, Y = 0) with one grey group
