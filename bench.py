@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-accounting", action="store_true",
                     help="time the headline steps without the photon accounting (a4)")
     ap.add_argument("--transport-path", choices=["auto", "cell", "zmarch"], default="auto")
+    ap.add_argument("--chem-path", choices=["auto", "two-pass", "one-pass"], default="auto")
     ap.add_argument("--shadow-myr", type=float, default=15.0, help="simulated time of --form shadow [Myr]")
     ap.add_argument("--smooth", action="store_true", help="time the smoothed RT step (Sec. 4.4) instead")
     ap.add_argument("--n-floor", type=float, default=None,
@@ -114,7 +115,7 @@ def cpu_baseline(seconds, n_full, M):
 
 
 def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, floor=0.0, nH_mean=1e-3, otsa=True,
-             a=1.0, acct=False, path="auto"):
+             a=1.0, acct=False, path="auto", chem_path="auto"):
     """The lognormal n^3 x 3 workload: build it, run `warmup` steps, reload
     the initial state, then time `steps` rt_step calls from it (injection,
     transport, the chemistry passes and, with acct, the photon accounting and
@@ -143,6 +144,7 @@ def grid_run(n, fp32, flux_name, steps, warmup, head_attempts, smooth=False, flo
         ctx.set_expansion(a)
     ctx.set_sources(ijk, ctx.source_rates(nd))
     ctx.set_transport_path(path)
+    ctx.set_chem_path(chem_path)
     dt = ctx.courant_dt()
     if head_attempts > 0:
         ctx.set_tuning(head_attempts, -1)
@@ -386,7 +388,9 @@ def adjoint_cost(steps=300, every=20):
     """Cost of the gradient of L = sum (x_HII - target)^2 after `steps`
     steps of the differentiation workload (64^3, one grey group, hydrogen
     only, 16 sources, FP64) with checkpoints every `every` steps, against
-    the plain forward run (rt_step, no checkpoints) on the same GPU."""
+    the plain forward run (rt_step, no checkpoints) on the same GPU; and the
+    same gradient in the mixed form (FP32 radiation in the forward steps)
+    with its cost and its distance from the FP64 gradient."""
     import numpy as np
     import torch
 
@@ -399,39 +403,69 @@ def adjoint_cost(steps=300, every=20):
     st = ri.initial_state(w)
     lnnd = torch.tensor(np.log(nd), dtype=torch.float64)
     lnnH = torch.tensor(np.log(st["nH"]), dtype=torch.float64, device="cuda")
-    plain = RTContext.for_workload(w)
-    dt = plain.courant_dt()
-    ctx = RTContext.for_workload(w, counters=True)
-    run = GradientRun(ctx, ijk, dt, steps, x0=w.xHII0, T0=w.T0, every=every)
 
-    def t_plain():
-        plain.load_state(st)
-        plain.set_sources(ijk, nd.reshape(-1, 1))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain.step(dt, steps)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
+    def t_plain(fp32):
+        plain = RTContext.for_workload(w, fp32=fp32)
+        dt = plain.courant_dt()
+        best = None
+        for _ in range(3):
+            plain.load_state(st)
+            plain.set_sources(ijk, nd.reshape(-1, 1))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plain.step(dt, steps)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        plain.close()
+        return best, dt
 
-    target = run.forward(torch.tensor(ri.perturbed_log_rates(nd, w.seed)), lnnH).clone()
-    tp = min(t_plain() for _ in range(3))
-    times = []
-    for _ in range(2):  # the first pass warms the allocator
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x = run.forward(lnnd, lnnH)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        g_src, g_nH = run.backward(2.0 * (x - target))[:2]
-        torch.cuda.synchronize()
-        times.append((t1 - t0, time.perf_counter() - t1))
-    tf, tb = times[-1]
-    return {"workload": f"grey {w.n[0]}^3 x 1 group, H only, 16 sources, {steps} steps, checkpoints every {every}, "
-                        "GLF, FP64",
+    target = None
+    out = {}
+    grads = {}
+    for fp32 in (False, True):
+        tp, dt = t_plain(fp32)
+        ctx = RTContext.for_workload(w, counters=True, fp32=fp32)
+        run = GradientRun(ctx, ijk, dt, steps, x0=w.xHII0, T0=w.T0, every=every)
+        if target is None:
+            target = run.forward(torch.tensor(ri.perturbed_log_rates(nd, w.seed)), lnnH).clone()
+        times = []
+        for _ in range(2):  # the first pass warms the allocator
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = run.forward(lnnd, lnnH)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            g_src, g_nH = run.backward(2.0 * (x - target))[:2]
+            torch.cuda.synchronize()
+            times.append((t1 - t0, time.perf_counter() - t1))
+        tf, tb = times[-1]
+        grads[fp32] = (float(((x - target) ** 2).sum().item()), g_src.cpu().numpy(), g_nH.cpu().numpy())
+        out["mixed" if fp32 else "fp64"] = {
             "forward_ms": tp * 1e3, "forward_checkpointed_ms": tf * 1e3, "backward_ms": tb * 1e3,
             "ratio": (tf + tb) / tp, "backward_only_ratio": tb / tp,
             "trace_entries_max": run.last_backward.get("trace_entries_max"),
             "grad_finite": bool(torch.isfinite(g_src).all().item() and torch.isfinite(g_nH).all().item())}
+        ctx.close()
+        del run, ctx
+        torch.cuda.empty_cache()
+    (L64, s64, n64), (L32, s32, n32) = grads[False], grads[True]
+    rng = np.random.default_rng(5)
+    dirs = [rng.standard_normal(n64.shape) for _ in range(4)]
+    d64 = np.array([np.sum(n64 * v) for v in dirs])
+    d32 = np.array([np.sum(n32 * v) for v in dirs])
+    out["mixed_vs_fp64"] = {"loss": abs(L32 - L64) / abs(L64),
+                            "source_gradients_e_inf": float(np.max(np.abs(s32 - s64)) / np.max(np.abs(s64))),
+                            "source_gradients_max_rel": float(np.max(np.abs(s32 - s64) / np.abs(s64))),
+                            "density_directions_max_rel": float(np.max(np.abs(d32 - d64) / np.abs(d64))),
+                            "density_gradient_e_inf": float(np.max(np.abs(n32 - n64)) / np.max(np.abs(n64)))}
+    f = out["fp64"]
+    return {"workload": f"grey {w.n[0]}^3 x 1 group, H only, 16 sources, {steps} steps, checkpoints every {every}, "
+                        "GLF, FP64 (and the mixed form)",
+            "forward_ms": f["forward_ms"], "forward_checkpointed_ms": f["forward_checkpointed_ms"],
+            "backward_ms": f["backward_ms"], "ratio": f["ratio"], "backward_only_ratio": f["backward_only_ratio"],
+            "trace_entries_max": f["trace_entries_max"], "grad_finite": f["grad_finite"],
+            "mixed": out["mixed"], "mixed_vs_fp64": out["mixed_vs_fp64"]}
 
 
 def host_cpu():
@@ -498,9 +532,10 @@ def timed_config(w, fp32, steps, warmup, ijk, nd, st=None, acct=False):
     ctx.load_state(st)
     ctx.set_sources(ijk, ctx.source_rates(nd))
     dt = ctx.courant_dt()
-    ctx.step(dt, warmup)
-    torch.cuda.synchronize()
-    ctx.load_state(st)
+    if warmup > 0:
+        ctx.step(dt, warmup)
+        torch.cuda.synchronize()
+        ctx.load_state(st)
     ctx.reset_stats()
     ctx.set_accounting(acct)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
@@ -650,9 +685,10 @@ def bench_precision(args):
 def bench_oracle_timing(args):
     """The oracle's own throughput on this host at 1 thread and on all the
     threads it may use: C1 (100 steps), C2 (200 steps on all threads, the
-    first 20 on one), the C3 64^3 sub-box (100 steps), 3 late steps of the
-    full 256^3 C3 grid from the FP64 GPU state after step 97 (compared with
-    the GPU's steps 98-100), and C5's forward run (300 steps)."""
+    first 20 on one), the C3 64^3 sub-box (100 steps), late steps of the
+    full 256^3 C3 grid from the FP64 GPU state after step 97 (3 on all
+    threads, compared with the GPU's steps 98-100; 1 on one thread), and
+    C5's forward run (300 steps)."""
     import torch
 
     import oracle
@@ -697,10 +733,11 @@ def bench_oracle_timing(args):
     del ctx
     torch.cuda.empty_cache()
     r = {}
-    for th in (full_threads, 1):
-        st = {k: v.copy() for k, v in s97.items()}
-        t, cgu = oracle_run(w3, st, i3, n3, 3, th, "C3 256^3 steps 98-100", dt=dt3)
-        r[f"threads_{th}"] = {"steps": 3, "seconds": t, "value": cgu}
+    # one thread takes step 98 only (a minute or more of host time)
+    for th, k in ((1, 1), (full_threads, 3)):
+        st = {key: v.copy() for key, v in s97.items()}
+        t, cgu = oracle_run(w3, st, i3, n3, k, th, "C3 256^3 from step 97", dt=dt3)
+        r[f"threads_{th}"] = {"steps": k, "seconds": t, "value": cgu}
     r["fp64_gpu_vs_oracle_after_step_100"] = {k: v["e_inf"] for k, v in field_errors(g100, st, 3).items()}
     runs["C3 256^3 x 3 steps 98-100"] = r
     out["runs"] = runs
@@ -795,13 +832,14 @@ def main():
     acct = not args.no_accounting
     floor = args.n_floor if args.n_floor is not None else (1e-12 if args.smooth else 0.0)
     r = grid_run(n, fp32, args.flux, args.steps, args.warmup, args.head_attempts, args.smooth, floor,
-                 otsa=not args.no_otsa, a=args.expansion, acct=acct, path=args.transport_path)
+                 otsa=not args.no_otsa, a=args.expansion, acct=acct, path=args.transport_path,
+                 chem_path=args.chem_path)
     w, M, K, s, ms, cgu, per = r["w"], r["M"], args.steps, r["stats"], r["ms"], r["cgu"], r["per"]
 
     rad, gas = algorithmic_bytes(M, fp32)
     default_config = (fp32 and n == 256 and args.flux == "hll" and not args.smooth and floor == 0.0
                       and not args.no_otsa and args.expansion == 1.0 and acct and args.head_attempts == 0
-                      and args.transport_path == "auto")
+                      and args.transport_path == "auto" and args.chem_path == "auto")
     window = (args.warmup + 1, args.warmup + K)
     split = per["transport"] > 0.0
     # the dominant kernel: the first chemistry pass (which on the per-cell

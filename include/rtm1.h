@@ -285,6 +285,20 @@ rt_status rt_step_noalloc(rt_ctx *ctx, double dt, int nsteps);
 enum { RT_PATH_AUTO = 0, RT_PATH_CELL = 1, RT_PATH_ZMARCH = 2 };
 rt_status rt_set_transport_path(rt_ctx *ctx, int path);
 
+/* Kernel arrangement of the chemistry that follows a separate transport
+ * (rt_thermochem, and rt_step on the z-marching path; App. A); results are
+ * the same bits on every path:
+ *   RT_CHEM_AUTO      one pass
+ *   RT_CHEM_TWO_PASS  a head pass of head_attempts attempts per cell in
+ *                     lockstep, then the queued cells in a persistent tail
+ *   RT_CHEM_ONE_PASS  one persistent pass whose lanes take the next cell as
+ *                     soon as theirs has filled dt_RT, cells whose previous
+ *                     pass took many attempts first
+ * The per-cell transport path's rt_step always runs its fused head pass and
+ * the tail. */
+enum { RT_CHEM_AUTO = 0, RT_CHEM_TWO_PASS = 1, RT_CHEM_ONE_PASS = 2 };
+rt_status rt_set_chem_path(rt_ctx *ctx, int path);
+
 /* Launch tuning (results do not depend on it): head_attempts = chemistry
  * attempts per cell in the first pass before a cell is queued for the
  * compacted second pass (1..1000000); queue_cap = queue capacity in cells,
@@ -330,9 +344,10 @@ rt_status rt_build_hll_table(int nf, int nth, double *out);
 #define RT_TIMING_CLASSES 6
 typedef struct {
     double ms[RT_TIMING_CLASSES];  /* inject, transport, chemistry head (fused
-                                      with transport on the per-cell path),
-                                      chemistry tail, other (adjoint passes),
-                                      photon accounting (reductions, ledger) */
+                                      with transport on the per-cell path; the
+                                      whole one-pass chemistry), chemistry
+                                      tail, other (adjoint passes), photon
+                                      accounting (reductions, ledger) */
     long long launches[RT_TIMING_CLASSES];
 } rt_timing;
 rt_status rt_set_timing(rt_ctx *ctx, int enabled);

@@ -21,7 +21,7 @@ EXPORTED = [
     "rt_init", "rt_scratch_bytes", "rt_bind", "rt_set_stream", "rt_current", "rt_set_current",
     "rt_set_sources", "rt_courant_dt", "rt_inject", "rt_transport", "rt_thermochem", "rt_step",
     "rt_get_stats", "rt_reset_stats", "rt_group_attributes", "rt_hll_table", "rt_build_hll_table",
-    "rt_last_error", "rt_free", "rt_set_tuning", "rt_set_transport_path", "rt_set_timing", "rt_get_timing",
+    "rt_last_error", "rt_free", "rt_set_tuning", "rt_set_transport_path", "rt_set_chem_path", "rt_set_timing", "rt_get_timing",
     "rt_batch_init", "rt_batch_scratch_bytes", "rt_batch_bind", "rt_batch_set_stream", "rt_batch_current",
     "rt_batch_set_current", "rt_batch_set_sources", "rt_batch_courant_dt", "rt_batch_step", "rt_batch_set_tuning", "rt_batch_get_stats",
     "rt_batch_reset_stats", "rt_batch_last_error", "rt_batch_free",
@@ -125,6 +125,8 @@ def lib():
     L.rt_set_tuning.restype = st
     L.rt_set_transport_path.argtypes = [vp, ctypes.c_int]
     L.rt_set_transport_path.restype = st
+    L.rt_set_chem_path.argtypes = [vp, ctypes.c_int]
+    L.rt_set_chem_path.restype = st
     L.rt_set_timing.argtypes = [vp, ctypes.c_int]
     L.rt_set_timing.restype = st
     L.rt_get_timing.argtypes = [vp, ctypes.POINTER(RtTiming)]

@@ -49,6 +49,7 @@ struct rt_ctx {
     unsigned qcap = 0;               // chemistry queue capacity (cells)
     unsigned qcap_max = 0;           // capacity the scratch size is computed for
     int head_attempts = HEAD_ATTEMPTS;
+    int chem_path = RT_CHEM_AUTO;     // chemistry after a separate transport: one pass or head + tail
     // kernel arrangement of the transport (rt_set_transport_path) and the
     // transport blocks whose accounting partials the step's ledger sums
     int path = RT_PATH_AUTO;
@@ -814,6 +815,16 @@ static rt_status do_chem(rt_ctx *c, double dt)
         if (r != RT_OK) return r;
     }
     unsigned long long *hist = c->acct ? c->dstats->hist : nullptr;
+    if (c->chem_path != RT_CHEM_TWO_PASS) {
+        rt_status r = timed(c, TM_HEAD, [&]() -> rt_status {
+            RT_HIP(c, launch_chem_all(c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur],
+                                      c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc,
+                                      c->st.natt, q, hist, sm, c->a_cosmo, prev_att(c), c->dstats, c->stream));
+            return RT_OK;
+        });
+        if (r != RT_OK) return r;
+        return c->acct ? acct_close(c, dt) : RT_OK;
+    }
     for (int part = 1; part <= 2; ++part) {
         rt_status r = timed(c, part == 1 ? TM_HEAD : TM_TAIL, [&]() -> rt_status {
             RT_HIP(c, launch_chem(part, c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur], c->st.xHII,
@@ -978,6 +989,15 @@ extern "C" rt_status rt_set_transport_path(rt_ctx *c, int path)
     if (path == RT_PATH_ZMARCH && !transport_z_fits(c->fp32, c->grid))
         RT_FAIL(c, RT_EINVAL, "the z-marching transport needs nx <= %d", c->fp32 ? 1024 : 512);
     c->path = path;
+    return RT_OK;
+}
+
+extern "C" rt_status rt_set_chem_path(rt_ctx *c, int path)
+{
+    if (!c) return RT_EINVAL;
+    if (path < RT_CHEM_AUTO || path > RT_CHEM_ONE_PASS)
+        RT_FAIL(c, RT_EINVAL, "path must be RT_CHEM_AUTO, _TWO_PASS or _ONE_PASS");
+    c->chem_path = path;
     return RT_OK;
 }
 

@@ -518,6 +518,14 @@ constexpr int QV_SMOOTH = QV_GRID + 6;
 #define RT_TAIL_CHUNK 64
 #endif
 constexpr unsigned TAIL_CHUNK = RT_TAIL_CHUNK;
+// positions a wave of the one-pass chemistry reserves at a time once past
+// the long chains (measured at 256^3 x 3: 64 -> 4.73 ms, 128 -> 4.30,
+// 256 -> 4.27, 512 -> 4.29, 1024 -> 5.54 ms, the last from the imbalance
+// at the end)
+#ifndef RT_CHEM_SWEEP_CHUNK
+#define RT_CHEM_SWEEP_CHUNK 256
+#endif
+constexpr unsigned CHEM_SWEEP_CHUNK = RT_CHEM_SWEEP_CHUNK;
 
 __device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CS &) {}
 __device__ __forceinline__ void q_store_rates(const QueueView &q, uint32_t p, const CSR &s)
@@ -607,8 +615,13 @@ __device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CSR &s, int 
 
 // Write a finished cell: N, the flux in the destination scaled by fs (with
 // smoothed RT: fs F^t + fb (F' - F^t)/dt_RT), the gas state and the counters.
+// The previous-pass attempt count kept per cell: the count, capped at 127,
+// in bits 0-6; bit 7 marks a cell the chemistry pass takes from its list of
+// long chains (it is then passed over in the sweep over all cells).
+constexpr uint8_t ATT_MASK = 0x7F, ATT_LISTED = 0x80;
+
 template <typename R, int M, class S>
-__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const S &s, double T)
+__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const S &s, double T, uint8_t mark = 0)
 {
     const size_t nc = io.ncell;
 #pragma unroll
@@ -627,7 +640,7 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
     io.T[i] = T;
     if (io.nacc) io.nacc[i] = s.acc;
     if (io.natt) io.natt[i] = s.att;
-    if (io.prev_att) io.prev_att[i] = (uint8_t)(s.att < 255 ? s.att : 255);
+    if (io.prev_att) io.prev_att[i] = (uint8_t)(mark | (s.att < (int)ATT_MASK ? s.att : (int)ATT_MASK));
 }
 
 }  // namespace rtm1

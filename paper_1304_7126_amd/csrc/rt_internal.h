@@ -155,6 +155,11 @@ struct ChemIO {
 };
 
 constexpr int TAIL_BLOCKS = 1024;
+// workgroups of the one-pass chemistry kernel (persistent; 256 threads each)
+#ifndef RT_CHEM_ALL_BLOCKS
+#define RT_CHEM_ALL_BLOCKS 1024
+#endif
+constexpr int CHEM_ALL_BLOCKS = RT_CHEM_ALL_BLOCKS;
 constexpr int HEAD_ATTEMPTS = 3;
 
 // bytes of scratch for a queue of cap cells (after the reduction partials),
@@ -164,6 +169,14 @@ size_t queue_bytes(unsigned cap, bool smooth);
 size_t queue_cell_bytes(bool smooth);
 // cap: cells the kernels may queue; layout_cap: capacity the scratch is laid out for
 QueueView queue_view(void *scratch, unsigned cap, unsigned layout_cap);
+
+// the chemistry in one persistent pass over all cells (same results as the
+// head and tail passes); the queue's counters and cell array hold its
+// position counter and its list of long chains
+hipError_t launch_chem_all(bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F,
+                           double *xHII, double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc,
+                           int32_t *natt, const QueueView &q, unsigned long long *hist, const SmoothArgs *sm, double a,
+                           uint8_t *prev_att, DevStats *stats, hipStream_t s);
 
 // part 1: queue reset + head pass; part 2: tail pass
 hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F, double *xHII,

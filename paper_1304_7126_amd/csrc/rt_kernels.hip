@@ -304,7 +304,8 @@ __global__ __launch_bounds__(256, (head_waves<R, M>())) void k_head(KGrid g, con
     // longest chains start first instead of draining the tail at its end.
     const bool want = !done;
     const int cls = !want ? 3
-                          : (io.prev_att && io.prev_att[i] >= TAIL_LONG_ATTEMPTS) ? 0 : (s.acc == 0 ? 1 : 2);
+                          : (io.prev_att && (io.prev_att[i] & ATT_MASK) >= TAIL_LONG_ATTEMPTS) ? 0
+                                                                                                 : (s.acc == 0 ? 1 : 2);
     unsigned p = ~0u;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -431,6 +432,194 @@ __global__ void k_zero_u32(unsigned *p, int n)
     for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0u;
 }
 
+// Before the one-pass chemistry: the cells whose previous pass took at least
+// TAIL_LONG_ATTEMPTS attempts go to a list (the queue's cell array, as many
+// as it holds) that the pass takes first, and are marked ATT_LISTED; every
+// other mark is cleared.  The count of such cells goes to *cnt (it may
+// exceed cap).
+__global__ __launch_bounds__(256) void k_long_list(uint8_t *__restrict__ prev, size_t nc, int32_t *__restrict__ list,
+                                                   unsigned cap, unsigned *__restrict__ cnt)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint8_t o = 0, v = 0;
+    bool want = false;
+    if (i < nc) {
+        o = prev[i];
+        v = (uint8_t)(o & ATT_MASK);
+        want = v >= TAIL_LONG_ATTEMPTS;
+    }
+    const unsigned long long m = __ballot(want);
+    bool listed = false;
+    if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned base = 0;
+        if (lane_id() == leader) base = atomicAdd(cnt, (unsigned)__popcll(m));
+        base = __shfl(base, leader);
+        if (want) {
+            const unsigned k = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+            if (k < cap) {
+                list[k] = (int32_t)i;
+                listed = true;
+            }
+        }
+    }
+    const uint8_t nv = listed ? (uint8_t)(v | ATT_LISTED) : v;
+    if (i < nc && nv != o) prev[i] = nv;
+}
+
+// The chemistry of every cell in one persistent launch (the pass after a
+// separate transport): each lane takes a cell, runs its attempts one per
+// loop trip (an attempt that fails the photon check repeats at once with the
+// halved substep), writes it when it has filled dt_RT and takes the next,
+// from its wave's reservation of positions.  Positions run over the list of
+// long chains first (their waves issue ahead of the others), then over all
+// cells in grid order, passing over the listed ones.  Every cell goes
+// through the same attempt code as in the head and tail passes, so results
+// are those of the two-pass chemistry bit for bit; what changes is that a
+// lane whose cell is done no longer idles until its wave's other lanes are.
+template <typename R, int M, int V>
+__global__ __launch_bounds__(256, 3) void k_chem_all(const KChem *__restrict__ kp, double dt, ChemIO<R> io, QueueView q,
+                                                     DevStats *__restrict__ st)
+{
+    const KChem &k = *kp;
+    constexpr bool SM = (V & V_SMOOTH) != 0;
+    const size_t nc = io.ncell;
+    const unsigned nl = io.prev_att ? min(*q.cnt[0], q.cap) : 0u;
+    const unsigned n = nl + (unsigned)nc;
+    std::conditional_t<SM, CSR, CS> s;
+    uint32_t cell = 0;
+    CC cc{1.0, 0.0, 0.0, 0.0};
+    bool active = false, exhausted = false, raised = false;
+    uint8_t mark = 0;
+    unsigned rbase = 0, ravail = 0;  // positions this wave has reserved and not yet handed out
+    unsigned fl = 0, cfl = 0;        // flags of the lane, flags of its current cell
+    unsigned long long a_acc = 0, a_att = 0, a_max = 0;
+    __shared__ unsigned s_hist[64];
+    if (io.hist) hist_init(s_hist);
+    // the cell's state as the head pass loads it, without the check of its
+    // fluxes; returns chem_init's verdict
+    auto load = [&](uint32_t c, bool fin) -> bool {
+        const size_t i = c;
+#pragma unroll
+        for (int grp = 0; grp < CM; ++grp) {
+            s.N[grp] = 0.0;
+            s.fs[grp] = 1.0;
+            if constexpr (SM) s.Nr[grp] = 0.0;
+        }
+#pragma unroll
+        for (int grp = 0; grp < M; ++grp) s.N[grp] = (double)io.N[(size_t)grp * nc + i] * io.ia3;
+        if constexpr (SM) {
+            const int si = io.sm.map ? io.sm.map[i] : -1;
+#pragma unroll
+            for (int grp = 0; grp < M; ++grp) {
+                const double nt =
+                    (si >= 0 ? io.sm.prev[(size_t)si * M + grp] : (double)io.sm.N[(size_t)grp * nc + i]) * io.ia3;
+                s.Nr[grp] = (s.N[grp] - nt) / dt;
+                s.N[grp] = nt;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.sm.F[(size_t)(3 * grp + d) * nc + i]);
+            }
+        }
+        s.x = io.xHII[i];
+        s.y2 = io.xHeII[i];
+        s.y3 = io.xHeIII[i];
+        cc = make_cc(k, io.nH[i] * io.ia3, io.T[i]);
+        return chem_init<CM, V>(k, dt, cc.Tiso, fin, s);
+    };
+    // write a cell whose chemistry has ended.  Its fluxes are checked here,
+    // where they are read anyway: a non-finite one means the cell is
+    // written back as loaded (what the head pass does when it finds one
+    // before the chemistry), and the flags of the discarded attempts are
+    // dropped
+    auto finish = [&]() {
+        bool fin = true;
+#pragma unroll
+        for (int grp = 0; grp < M; ++grp)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.F[(size_t)(3 * grp + d) * nc + cell]);
+        if (!fin) {
+            load(cell, false);
+            cfl = 2u;
+        }
+        fl |= cfl;
+        const double T = chem_finish<CM>(k, cc, s, fl);
+        store_cell<R, M>(io, cell, s, T, mark);
+        if (io.hist) hist_add(s_hist, s.acc);
+        a_acc += (unsigned long long)s.acc;
+        a_att += (unsigned long long)s.att;
+        a_max = a_max > (unsigned long long)s.att ? a_max : (unsigned long long)s.att;
+    };
+    while (true) {
+        if (!exhausted) {
+            bool first = false;
+            const bool need = !active;
+            const unsigned long long m = __ballot(need);
+            if (m) {
+                const unsigned nneed = (unsigned)__popcll(m);
+                const unsigned r = (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+                unsigned t;
+                if (ravail >= nneed) {
+                    t = rbase + r;
+                    rbase += nneed;
+                    ravail -= nneed;
+                } else {
+                    // one wave's width at a time among the long chains, so
+                    // that a wave does not hold a second set of them; more
+                    // in the sweep, where each reservation is an atomic on
+                    // the one counter every wave shares
+                    const unsigned more = nneed - ravail;
+                    const unsigned chunk = rbase < nl ? TAIL_CHUNK : CHEM_SWEEP_CHUNK;
+                    const unsigned take = more > chunk ? more : chunk;
+                    const int leader = __ffsll((long long)m) - 1;
+                    unsigned base = 0;
+                    if (lane_id() == leader) base = atomicAdd(q.head, take);
+                    base = __shfl(base, leader);
+                    t = r < ravail ? rbase + r : base + (r - ravail);
+                    rbase = base + more;
+                    ravail = take - more;
+                }
+                if (rbase >= n) exhausted = true;
+                if (need && t < n) {
+                    bool take = true;
+                    if (t < nl) {
+                        cell = (uint32_t)q.cell[t];
+                        mark = ATT_LISTED;
+                        first = true;
+                    } else {
+                        cell = t - nl;
+                        mark = 0;
+                        take = !io.prev_att || !(io.prev_att[cell] & ATT_LISTED);
+                    }
+                    if (take) {
+                        cfl = 0;
+                        if (load(cell, true)) {
+                            active = true;
+                        } else {
+                            // a non-finite input: the cell is written back as loaded
+                            cfl = 2u;
+                            finish();
+                        }
+                    }
+                }
+            }
+            if (!raised && __any(first)) {
+                __builtin_amdgcn_s_setprio(3);
+                raised = true;
+            }
+        }
+        if (!__any(active)) {
+            if (exhausted) break;
+            continue;
+        }
+        if (active && chem_attempt<CM, V>(k, cc, s, cfl)) {
+            finish();
+            active = false;
+        }
+    }
+    if (io.hist) hist_flush(s_hist, io.hist);
+    block_stats(st, a_acc, a_att, a_max, fl);
+}
+
 // part 1: reset the queue counters and run the head pass; part 2: the tail
 template <typename R, int M, int FUSE, int FLUX, int V>
 static void launch_head_tail(int part, const KGrid &g, const KChem &kc, const KChem *dk, double dt, R c, R kdx, const void *Nin,
@@ -512,6 +701,56 @@ hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, con
         ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a,
                                             prev_att);
         dispatch_SM<double, 0, 0>(part, g, kc, dk, dt, 0.0, 0.0, nullptr, nullptr, io, nullptr, 0, 0, q, K, stats, s);
+    }
+    return hipGetLastError();
+}
+
+// one-pass chemistry: queue counters reset, the list of long chains, then
+// the persistent kernel
+template <typename R, int M, int V>
+static void launch_all(const KChem *dk, double dt, const ChemIO<R> &io, const QueueView &q, DevStats *st,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 65);
+    if (io.prev_att && io.ncell > 0)
+        hipLaunchKernelGGL(k_long_list, dim3((unsigned)((io.ncell + 255) / 256)), dim3(256), 0, s, io.prev_att, io.ncell,
+                           q.cell, q.cap, q.cnt[0]);
+    hipLaunchKernelGGL((k_chem_all<R, M, V>), dim3(CHEM_ALL_BLOCKS), dim3(256), 0, s, dk, dt, io, q, st);
+}
+
+template <typename R, int V>
+static void dispatch_all_M(const KChem &kc, const KChem *dk, double dt, const ChemIO<R> &io, const QueueView &q,
+                           DevStats *st, hipStream_t s)
+{
+    if (kc.M == 1) launch_all<R, 1, V>(dk, dt, io, q, st, s);
+    else if (kc.M == 2) launch_all<R, 2, V>(dk, dt, io, q, st, s);
+    else launch_all<R, 3, V>(dk, dt, io, q, st, s);
+}
+
+template <typename R>
+static void dispatch_all(const KChem &kc, const KChem *dk, double dt, const ChemIO<R> &io, const QueueView &q,
+                         DevStats *st, hipStream_t s)
+{
+    const int v = (io.sm.N ? V_SMOOTH : 0) | (kc.otsa ? 0 : V_CASE_A);
+    if (v == 0) dispatch_all_M<R, 0>(kc, dk, dt, io, q, st, s);
+    else if (v == 1) dispatch_all_M<R, 1>(kc, dk, dt, io, q, st, s);
+    else if (v == 2) dispatch_all_M<R, 2>(kc, dk, dt, io, q, st, s);
+    else dispatch_all_M<R, 3>(kc, dk, dt, io, q, st, s);
+}
+
+hipError_t launch_chem_all(bool fp32, const KGrid &g, const KChem &kc, const KChem *dk, double dt, void *N, void *F,
+                           double *xHII, double *xHeII, double *xHeIII, double *T, const double *nH, int32_t *nacc,
+                           int32_t *natt, const QueueView &q, unsigned long long *hist, const SmoothArgs *sm, double a,
+                           uint8_t *prev_att, DevStats *stats, hipStream_t s)
+{
+    if (fp32) {
+        ChemIO<float> io = make_io<float>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt, a,
+                                          prev_att);
+        dispatch_all<float>(kc, dk, dt, io, q, stats, s);
+    } else {
+        ChemIO<double> io = make_io<double>(g.ncell, N, F, xHII, xHeII, xHeIII, T, nH, nacc, natt, nullptr, hist, sm, dt,
+                                            a, prev_att);
+        dispatch_all<double>(kc, dk, dt, io, q, stats, s);
     }
     return hipGetLastError();
 }
@@ -698,15 +937,69 @@ __global__ __launch_bounds__(256) void k_reduce_final(const RedOut *__restrict__
     }
 }
 
+// Four consecutive values of a group plane (16-byte aligned): one 16-byte
+// load for FP32, two for FP64.
+__device__ __forceinline__ void load4(const float *p, double v[4])
+{
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+}
+__device__ __forceinline__ void load4(const double *p, double v[4])
+{
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+
 // Photons per group of one radiation set, for the step's ledger: per block
 // the sum of N of each group (grid-stride in a fixed order, wave
-// butterflies, the four waves in order) at part[3 b + g].
+// butterflies, the four waves in order) at part[3 b + g].  When every group
+// plane starts 16-byte aligned a thread takes four consecutive cells per
+// round, two rounds' loads in flight before their sums.
 template <typename R>
 __global__ __launch_bounds__(RED_THREADS) void k_sum_n(size_t nc, int M, const R *__restrict__ N,
                                                        double *__restrict__ part)
 {
     double sg[3] = {0.0, 0.0, 0.0};
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (size_t)gridDim.x * blockDim.x)
+    const size_t T = (size_t)gridDim.x * blockDim.x, t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t i0 = 0;
+    if (((uintptr_t)N & 15) == 0 && ((nc * sizeof(R)) & 15) == 0) {
+        const size_t n4 = nc / 4;
+        size_t q = t0;
+        for (; q + T < n4; q += 2 * T) {
+            double v[3][2][4];
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+                if (g < M) {
+                    load4(N + (size_t)g * nc + 4 * q, v[g][0]);
+                    load4(N + (size_t)g * nc + 4 * (q + T), v[g][1]);
+                }
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+                if (g < M)
+#pragma unroll
+                    for (int r = 0; r < 2; ++r)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) sg[g] += v[g][r][j];
+        }
+        for (; q < n4; q += T) {
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+                if (g < M) {
+                    double v[4];
+                    load4(N + (size_t)g * nc + 4 * q, v);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sg[g] += v[j];
+                }
+        }
+        i0 = 4 * n4;
+    }
+    for (size_t i = i0 + t0; i < nc; i += T)
         for (int g = 0; g < M; ++g) sg[g] += (double)N[(size_t)g * nc + i];
     __shared__ double s[RED_THREADS / 64][3];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;

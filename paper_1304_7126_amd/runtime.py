@@ -184,6 +184,13 @@ class RTContext:
         """Transport kernel arrangement: 'auto', 'cell' or 'zmarch' (same results)."""
         check(lib().rt_set_transport_path(self._h, self.PATHS[path]), self._h)
 
+    CHEM_PATHS = {"auto": 0, "two-pass": 1, "one-pass": 2}
+
+    def set_chem_path(self, path):
+        """Chemistry kernel arrangement after a separate transport: 'auto',
+        'two-pass' (head + tail) or 'one-pass' (same results)."""
+        check(lib().rt_set_chem_path(self._h, self.CHEM_PATHS[path]), self._h)
+
     def courant_dt(self, courant=0.8):
         v = ctypes.c_double()
         check(lib().rt_courant_dt(self._h, float(courant), ctypes.byref(v)), self._h)
