@@ -600,40 +600,44 @@ __device__ __forceinline__ uint32_t q_load(const KChem &k, const QueueView &q, u
 // Flux of group g of a finished cell from the transported flux fp in the
 // destination (and, smoothed, the pre-step flux ft of the source set).
 template <typename R>
-__device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CS &s, int g, size_t j, R fp)
+__device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CS &s, int g, R fp, R ft)
 {
     return (R)((double)fp * s.fs[g]);
 }
 template <typename R>
-__device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CSR &s, int g, size_t j, R fp)
+__device__ __forceinline__ R finish_flux(const ChemIO<R> &io, const CSR &s, int g, R fp, R ftr)
 {
     // a cell that accepted no substep keeps its pre-step state
-    const double ft = (double)io.sm.F[j];
+    const double ft = (double)ftr;
     if (s.acc == 0) return (R)ft;
     return (R)(s.fs[g] * ft + s.fb[g] * (((double)fp - ft) / io.sm.dt));
 }
 
-// Write a finished cell: N, the flux in the destination scaled by fs (with
-// smoothed RT: fs F^t + fb (F' - F^t)/dt_RT), the gas state and the counters.
 // The previous-pass attempt count kept per cell: the count, capped at 127,
 // in bits 0-6; bit 7 marks a cell the chemistry pass takes from its list of
 // long chains (it is then passed over in the sweep over all cells).
 constexpr uint8_t ATT_MASK = 0x7F, ATT_LISTED = 0x80;
 
+// Write a finished cell: N, the flux in the destination scaled by fs (with
+// smoothed RT: fs F^t + fb (F' - F^t)/dt_RT), the gas state and the counters.
+// The fluxes it rescales are loaded before anything is written: a load
+// issued after a store waits for that store (one counter tracks both), so
+// loads placed between the stores would each wait out the stores before
+// them.
 template <typename R, int M, class S>
 __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const S &s, double T, uint8_t mark = 0)
 {
+    constexpr bool SM = std::is_same<S, CSR>::value;
     const size_t nc = io.ncell;
+    R fp[3 * M], ft[3 * M];
 #pragma unroll
-    for (int g = 0; g < M; ++g) {
-        io.N[(size_t)g * nc + i] = (R)(s.N[g] * io.a3);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const size_t j = (size_t)(3 * g + d) * nc + i;
-            R &f = io.F[j];
-            f = finish_flux(io, s, g, j, f);
-        }
+    for (int j = 0; j < 3 * M; ++j) {
+        fp[j] = io.F[(size_t)j * nc + i];
+        if constexpr (SM) ft[j] = io.sm.F[(size_t)j * nc + i];
+        else ft[j] = fp[j];
     }
+#pragma unroll
+    for (int g = 0; g < M; ++g) io.N[(size_t)g * nc + i] = (R)(s.N[g] * io.a3);
     io.xHII[i] = s.x;
     io.xHeII[i] = s.y2;
     io.xHeIII[i] = s.y3;
@@ -641,6 +645,10 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
     if (io.nacc) io.nacc[i] = s.acc;
     if (io.natt) io.natt[i] = s.att;
     if (io.prev_att) io.prev_att[i] = (uint8_t)(mark | (s.att < (int)ATT_MASK ? s.att : (int)ATT_MASK));
+#pragma unroll
+    for (int g = 0; g < M; ++g)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) io.F[(size_t)(3 * g + d) * nc + i] = finish_flux(io, s, g, fp[3 * g + d], ft[3 * g + d]);
 }
 
 }  // namespace rtm1

@@ -4,8 +4,9 @@ against the two-pass chemistry (a lockstep head pass, then the queued cells
 in a persistent tail): the same bits in every field and the same counters,
 for both precisions, one to three groups, smoothed RT and the case without
 the on-the-spot approximation, over several steps of the split rt_step and
-for rt_thermochem alone; with a non-finite cell; and with a list of long
-chains larger than the room it has."""
+for rt_thermochem alone; with non-finite cells; with a list of long chains
+larger than the room it has; and on a grid large enough (over the 262,144
+lanes of the first fill) that most cells reach their lane as a refill."""
 import numpy as np
 import pytest
 import torch
@@ -114,4 +115,25 @@ def test_one_pass_thermochem_alone_with_a_nonfinite_cell(fp32):
         for _ in range(3):
             c.thermochem(dt)
     s = compare(*ctxs)
+    assert s["flags"] & 2
+
+
+@pytest.mark.parametrize("fp32", [True, False])
+def test_one_pass_refills_on_a_large_grid(fp32):
+    # 96^3 cells: 3.4x the lanes of the first fill, so that most cells are
+    # taken by lanes whose previous cell is done
+    w, (a, b) = lognormal_pair(96, fp32, 0.03, steps=3)
+    for c in (a, b):
+        st = c.state_numpy()
+        st["nH"] = c.nH.cpu().numpy()
+        # non-finite inputs late in the grid: a flux, a density, a temperature
+        st["F"][1, 2, 90, 91, 92] = np.nan
+        st["N"][0, 80, 3, 4] = np.inf
+        st["T"][70, 60, 50] = np.nan
+        c.load_state(st)
+    dt = a.courant_dt()
+    for _ in range(w.steps):
+        a.step(dt, 1)
+        b.step(dt, 1)
+    s = compare(a, b)
     assert s["flags"] & 2
