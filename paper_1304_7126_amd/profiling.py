@@ -73,7 +73,7 @@ def _write(path, title, command, body, figures):
     figures = dict(figures)
     figures["kernel_source_hash"] = kernel_source_hash()
     with open(path, "w") as f:
-        f.write(f"# {title}\n\nCommand (from /tmp with TMPDIR=/tmp, then from the repository root):\n\n")
+        f.write(f"# {title}\n\nCommands (the profiled run from /tmp, the summary from the repository root):\n\n")
         for c in command:
             f.write(f"    {c}\n")
         f.write("\n" + body.rstrip() + "\n\n")
