@@ -436,35 +436,51 @@ __global__ void k_zero_u32(unsigned *p, int n)
 // TAIL_LONG_ATTEMPTS attempts go to a list (the queue's cell array, as many
 // as it holds) that the pass takes first, and are marked ATT_LISTED; every
 // other mark is cleared.  The count of such cells goes to *cnt (it may
-// exceed cap).
+// exceed cap).  A thread takes four consecutive cells (one 4-byte word of
+// counts; the array is padded to 256 bytes).
 __global__ __launch_bounds__(256) void k_long_list(uint8_t *__restrict__ prev, size_t nc, int32_t *__restrict__ list,
                                                    unsigned cap, unsigned *__restrict__ cnt)
 {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint8_t o = 0, v = 0;
-    bool want = false;
-    if (i < nc) {
-        o = prev[i];
-        v = (uint8_t)(o & ATT_MASK);
-        want = v >= TAIL_LONG_ATTEMPTS;
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // word index
+    const size_t i0 = 4 * q;
+    uint32_t o = 0;
+    if (i0 < nc) o = reinterpret_cast<const uint32_t *>(prev)[q];
+    unsigned want = 0;  // bit j: cell i0 + j is a long chain
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const unsigned v = (o >> (8 * j)) & ATT_MASK;
+        if (i0 + j < nc && v >= (unsigned)TAIL_LONG_ATTEMPTS) want |= 1u << j;
     }
-    const unsigned long long m = __ballot(want);
-    bool listed = false;
-    if (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        unsigned base = 0;
-        if (lane_id() == leader) base = atomicAdd(cnt, (unsigned)__popcll(m));
-        base = __shfl(base, leader);
-        if (want) {
-            const unsigned k = base + (unsigned)__popcll(m & ((1ull << lane_id()) - 1ull));
+    // this lane's first slot: the wanted cells of the lanes before it
+    const unsigned c = (unsigned)__popc(want);
+    unsigned ex = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned u = __shfl_up(ex, d, 64);
+        if (lane_id() >= d) ex += u;
+    }
+    const unsigned tot = __shfl(ex, 63, 64);
+    ex -= c;
+    unsigned base = 0;
+    if (tot) {
+        if (lane_id() == 0) base = atomicAdd(cnt, tot);
+        base = __shfl(base, 0, 64);
+    }
+    uint32_t nw = 0;
+    unsigned k = base + ex;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t b = (o >> (8 * j)) & ATT_MASK;
+        if (want & (1u << j)) {
             if (k < cap) {
-                list[k] = (int32_t)i;
-                listed = true;
+                list[k] = (int32_t)(i0 + j);
+                b |= ATT_LISTED;
             }
+            ++k;
         }
+        nw |= b << (8 * j);
     }
-    const uint8_t nv = listed ? (uint8_t)(v | ATT_LISTED) : v;
-    if (i < nc && nv != o) prev[i] = nv;
+    if (i0 < nc && nw != o) reinterpret_cast<uint32_t *>(prev)[q] = nw;
 }
 
 // The chemistry of every cell in one persistent launch (the pass after a
@@ -713,8 +729,8 @@ static void launch_all(const KChem *dk, double dt, const ChemIO<R> &io, const Qu
 {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, q.count, 65);
     if (io.prev_att && io.ncell > 0)
-        hipLaunchKernelGGL(k_long_list, dim3((unsigned)((io.ncell + 255) / 256)), dim3(256), 0, s, io.prev_att, io.ncell,
-                           q.cell, q.cap, q.cnt[0]);
+        hipLaunchKernelGGL(k_long_list, dim3((unsigned)((io.ncell + 1023) / 1024)), dim3(256), 0, s, io.prev_att,
+                           io.ncell, q.cell, q.cap, q.cnt[0]);
     hipLaunchKernelGGL((k_chem_all<R, M, V>), dim3(CHEM_ALL_BLOCKS), dim3(256), 0, s, dk, dt, io, q, st);
 }
 

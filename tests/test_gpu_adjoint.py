@@ -268,5 +268,6 @@ def test_mixed_gradient_close_to_fp64_at_full_size():
     print(f"mixed vs FP64 adjoint: L {e_L:.3e}, source gradients e_inf {e_src:.3e} (each {e_src_each:.3e}), "
           f"density directions {e_dir:.3e}, density gradient e_inf {e_cell:.3e}, per-cell p50 "
           f"{np.quantile(rel, 0.5):.3e} p99 {np.quantile(rel, 0.99):.3e} max {rel.max():.3e}", flush=True)
-    assert e_L <= 1e-3
-    assert e_src <= 1e-2 and e_dir <= 1e-2
+    # measured: loss 9.2e-7, sources 3.1e-6 (each 2.5e-5), directions 7.3e-6
+    assert e_L <= 1e-5
+    assert e_src <= 1e-4 and e_src_each <= 1e-3 and e_dir <= 1e-4

@@ -1,6 +1,8 @@
 """Parity at the benchmark's full size: 256^3 x 3 groups in the launch
-configuration bench.py times (rt_step: injection, fused transport + first
-chemistry pass, compacted tail), plain, smoothed and without OTSA.  After some steps on the GPU the pre-step
+configuration bench.py times (rt_step: injection, the z-marching transport,
+the one-pass chemistry, the photon accounting), plain, smoothed and without
+OTSA, and the dense-gas variant; 128^3 x 3 in FP64 over 200 steps.  After
+some steps on the GPU the pre-step
 state is copied to the host, the oracle steps sampled cells one by one from
 it (or_step_cells), and the GPU's next rt_step is compared on those cells."""
 import numpy as np
@@ -47,6 +49,7 @@ def run_and_sample(w, steps_before, fp32=False, smooth=False, floor=0.0, nsample
         ctx = RTContext.for_workload(w, fp32=fp32, counters=True, smooth=smooth, N_floor=floor)
         ctx.load_state(ri.initial_state(w))
         ctx.set_sources(ijk, ctx.source_rates(nd))
+        ctx.set_accounting(True)
     dt = ctx.courant_dt()
     if steps_before > done:
         ctx.step(dt, steps_before - done)

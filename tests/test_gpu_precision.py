@@ -1,11 +1,19 @@
-"""Precision form: FP32 N/F transport with FP64 chemistry against the FP64
-oracle and the FP64 GPU path, field by field, on a 64^3 box of the 256^3
-benchmark recipe (same cell size, density statistics and source rates).
+"""Precision form (FP32 N/F transport, FP64 chemistry) on the precision
+configuration's 64^3 sub-box: cells [0, 64)^3 of the 256^3 lognormal
+realisation with the sources inside them, run as a periodic box of its own
+(same cell size) for 100 steps, by the oracle, the FP64 GPU path and the
+mixed GPU path.  Errors per field and group: the global-normalised
+e_inf = max|a - b| / max|b| and quantiles of the per-cell relative error
+over cells with |b| > 1e-6 max|b|.
 
-The errors are written to precision_errors.json (in gpurun_out/ when that
-folder exists) and bounded here:
-  FP64 GPU vs oracle : e_inf <= 1e-10 on every field (measured ~1e-12)
-  mixed  vs oracle   : e_inf <= 2e-6 on every field (measured <= 3.4e-7)
+Bounds (measured values in brackets):
+  FP64 GPU vs oracle : e_inf <= 1e-10 on every field          [<= 1.2e-11]
+  mixed vs oracle    : e_inf <= 1e-5 on every field            [<= 2.1e-6]
+                       per-cell p99 <= 2e-5                    [<= 6.9e-6, F]
+                       per-cell p99.9 <= 1e-3                  [<= 2.5e-4, F]
+The per-cell tail is the flux of cells where |F| << c_r N, whose value
+comes out of a cancellation (an FP32 rounding of the stencil's c_r N is
+large against it); N, x and T stay below 3.6e-6 at p99.9.
 """
 import json
 import os
@@ -19,21 +27,19 @@ import rt_inputs as ri
 
 pytestmark = pytest.mark.gpu
 
-STEPS = 30
+STEPS = 100
 
 
 def errors(a, b):
-    """global-normalised e_inf and the largest per-cell relative error over
-    cells with |b| > 1e-6 max|b|."""
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
     sc = np.max(np.abs(b))
     if sc == 0:
-        return {"e_inf": float(np.max(np.abs(a))), "rel_max": 0.0}
+        return {"e_inf": float(np.max(np.abs(a))), "p99": 0.0, "p999": 0.0, "max": 0.0}
     m = np.abs(b) > 1e-6 * sc
     rel = np.abs(a[m] - b[m]) / np.abs(b[m])
-    return {"e_inf": float(np.max(np.abs(a - b)) / sc), "rel_max": float(rel.max()) if rel.size else 0.0,
-            "rel_p99": float(np.quantile(rel, 0.99)) if rel.size else 0.0}
+    return {"e_inf": float(np.max(np.abs(a - b)) / sc), "p99": float(np.quantile(rel, 0.99)),
+            "p999": float(np.quantile(rel, 0.999)), "max": float(rel.max())}
 
 
 def field_errors(g, st, M):
@@ -47,34 +53,34 @@ def field_errors(g, st, M):
     return out
 
 
-def test_precision_form_errors_against_fp64():
+def test_precision_form_on_the_subbox():
     assert torch.cuda.is_available()
     from paper_1304_7126_amd import RTContext
-    w = ri.lognormal_box(64, 13.2 * 64 / 256, 3, steps=STEPS, seed=0)
-    ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
+    w = ri.lognormal_256(steps=STEPS)
+    ws, st0, ijk, nd = ri.subbox(w, 64)
     res = {}
     for fp32 in (False, True):
-        ctx = RTContext.for_workload(w, fp32=fp32)
-        ctx.load_state(ri.initial_state(w))
+        ctx = RTContext.for_workload(ws, fp32=fp32)
+        ctx.load_state(st0)
         ctx.set_sources(ijk, ctx.source_rates(nd))
         dt = ctx.courant_dt()
         ctx.step(dt, STEPS)
         res[fp32] = ctx.state_numpy()
-    o = oracle.OracleRT.for_workload(w)
-    st = ri.initial_state(w)
+        ctx.close()
+    print(f"# oracle: {STEPS} steps of the 64^3 sub-box ({ws.n_sources} sources)", flush=True)
+    o = oracle.OracleRT.for_workload(ws)
+    st = {k: v.copy() for k, v in st0.items()}
     ondot = o.source_rates(nd)
     for _ in range(STEPS):
         o.step(st, dt, ijk, ondot)
-    M = w.spectrum.M
-    report = {"workload": f"lognormal 64^3 x {M} groups, same recipe as 256^3, {STEPS} steps",
+    M = ws.spectrum.M
+    report = {"workload": f"64^3 sub-box of the lognormal 256^3 x {M} realisation, {STEPS} steps",
               "fp64_gpu_vs_oracle": field_errors(res[False], st, M),
-              "mixed_gpu_vs_oracle": field_errors(res[True], st, M),
-              "mixed_gpu_vs_fp64_gpu": field_errors(res[True], res[False], M)}
-    out_dir = "gpurun_out" if os.path.isdir("gpurun_out") else "."
-    with open(os.path.join(out_dir, "precision_errors.json"), "w") as f:
-        json.dump(report, f, indent=1)
-    print(json.dumps(report["mixed_gpu_vs_oracle"]), flush=True)
+              "mixed_gpu_vs_oracle": field_errors(res[True], st, M)}
+    print(json.dumps(report), flush=True)
     for k, v in report["fp64_gpu_vs_oracle"].items():
         assert v["e_inf"] <= 1e-10, (k, v)
     for k, v in report["mixed_gpu_vs_oracle"].items():
-        assert v["e_inf"] <= 2e-6, (k, v)
+        assert v["e_inf"] <= 1e-5, (k, v)
+        assert v["p99"] <= 2e-5, (k, v)
+        assert v["p999"] <= 1e-3, (k, v)
