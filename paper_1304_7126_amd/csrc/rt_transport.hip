@@ -13,10 +13,12 @@
 //     of the pressure tensor and the speed pair along x and along y; the
 //     rows just outside the tile (y halo) are evaluated by the tile's edge
 //     threads.
-// The next plane's state is loaded one iteration ahead of its use.  Every
-// face flux is evaluated with the same functions and operands as the
-// per-cell transport (transport_cell), and a cell's six fluxes are summed in
-// the same order, so both give the same bits.
+// Each x- and y-face flux is evaluated once, by the cell on its low side,
+// and reaches the cell on its high side through LDS.  The next plane's
+// state is loaded one iteration ahead of its use.  Every face flux is
+// evaluated with the same functions and operands as the per-cell transport
+// (transport_cell), and a cell's six fluxes are summed in the same order,
+// so both give the same bits.
 #include "rt_cell.h"
 
 namespace rtm1 {
@@ -199,7 +201,9 @@ __device__ __forceinline__ void block_sum2(double a, double b, double &sa, doubl
 // The LDS records are double-buffered: a plane's records are written into
 // one buffer and read after one barrier; the next plane's go to the other
 // buffer, which every thread has finished reading once it passed that
-// barrier.
+// barrier.  The face fluxes are written after the first barrier of a plane
+// and read after the second; the next plane writes them only after its
+// first barrier, which every thread reaches once it has read them.
 // AHEAD: the plane above and the halo rows are loaded one plane before
 // their use (more registers); otherwise at the start of their plane.
 template <typename R, int FLUX, int NT, bool AHEAD>
@@ -209,6 +213,7 @@ __global__ __launch_bounds__(NT) void k_transport_z(KGrid g, int H, int zc, R c,
                                                     double *__restrict__ acct)
 {
     __shared__ R sh[2][XREC][NT];
+    __shared__ R shf[8][NT];  // the fluxes through each cell's +x and +y faces
     const int grp = blockIdx.z;
     const int t = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -280,39 +285,58 @@ __global__ __launch_bounds__(NT) void k_transport_z(KGrid g, int H, int zc, R c,
         if (act) publish<R, NT>(buf, t, cur);
         __syncthreads();
         if (act) {
-            R Pm[4], Pp[4];
-            R acc[4] = {R(0), R(0), R(0), R(0)};
-            double bout = 0.0;
-            // x faces
-            {
-                FaceSide<R> s;
-                if (tl >= 0) fetch<R, NT>(buf, tl, 0, s);
-                else side_of<R, FLUX>(tab, nf, nth, ghost_of(g, cur.u, 0, grp, c), 0, c, s);
-                face_flux<R, FLUX>(s.u, s.p, s.lm, s.lp, cur.u, cur.p, cur.lm[0], cur.lp[0], 0, c, Pm);
-            }
+            // the +x and +y faces: evaluated here, published for the cells
+            // on their other side, whose -x and -y faces they are
+            R Px[4], Py[4];
             {
                 FaceSide<R> s;
                 if (tr >= 0) fetch<R, NT>(buf, tr, 0, s);
                 else side_of<R, FLUX>(tab, nf, nth, ghost_of(g, cur.u, 1, grp, c), 0, c, s);
-                face_flux<R, FLUX>(cur.u, cur.p, cur.lm[0], cur.lp[0], s.u, s.p, s.lm, s.lp, 0, c, Pp);
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m) acc[m] += Pm[m] - Pp[m];
-            if (x == 0 && !perx) bout -= (double)Pm[0];
-            if (x == nx - 1 && !perx) bout += (double)Pp[0];
-            // y faces
-            {
-                FaceSide<R> s;
-                if (tdn >= 0) fetch<R, NT>(buf, tdn, 1, s);
-                else side_of<R, FLUX>(tab, nf, nth, tdn == -2 ? hdn_u : ghost_of(g, cur.u, 2, grp, c), 1, c, s);
-                face_flux<R, FLUX>(s.u, s.p, s.lm, s.lp, cur.u, cur.p, cur.lm[1], cur.lp[1], 1, c, Pm);
+                face_flux<R, FLUX>(cur.u, cur.p, cur.lm[0], cur.lp[0], s.u, s.p, s.lm, s.lp, 0, c, Px);
             }
             {
                 FaceSide<R> s;
                 if (tup >= 0) fetch<R, NT>(buf, tup, 1, s);
                 else side_of<R, FLUX>(tab, nf, nth, tup == -2 ? hup_u : ghost_of(g, cur.u, 3, grp, c), 1, c, s);
-                face_flux<R, FLUX>(cur.u, cur.p, cur.lm[1], cur.lp[1], s.u, s.p, s.lm, s.lp, 1, c, Pp);
+                face_flux<R, FLUX>(cur.u, cur.p, cur.lm[1], cur.lp[1], s.u, s.p, s.lm, s.lp, 1, c, Py);
             }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                shf[m][t] = Px[m];
+                shf[4 + m][t] = Py[m];
+            }
+        }
+        __syncthreads();
+        if (act) {
+            R Pm[4], Pp[4];
+            R acc[4] = {R(0), R(0), R(0), R(0)};
+            double bout = 0.0;
+            // x faces
+            if (tl >= 0) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) Pm[m] = shf[m][tl];
+            } else {
+                FaceSide<R> s;
+                side_of<R, FLUX>(tab, nf, nth, ghost_of(g, cur.u, 0, grp, c), 0, c, s);
+                face_flux<R, FLUX>(s.u, s.p, s.lm, s.lp, cur.u, cur.p, cur.lm[0], cur.lp[0], 0, c, Pm);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Pp[m] = shf[m][t];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc[m] += Pm[m] - Pp[m];
+            if (x == 0 && !perx) bout -= (double)Pm[0];
+            if (x == nx - 1 && !perx) bout += (double)Pp[0];
+            // y faces
+            if (tdn >= 0) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) Pm[m] = shf[4 + m][tdn];
+            } else {
+                FaceSide<R> s;
+                side_of<R, FLUX>(tab, nf, nth, tdn == -2 ? hdn_u : ghost_of(g, cur.u, 2, grp, c), 1, c, s);
+                face_flux<R, FLUX>(s.u, s.p, s.lm, s.lp, cur.u, cur.p, cur.lm[1], cur.lp[1], 1, c, Pm);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Pp[m] = shf[4 + m][t];
 #pragma unroll
             for (int m = 0; m < 4; ++m) acc[m] += Pm[m] - Pp[m];
             if (y == 0 && !pery) bout -= (double)Pm[0];
