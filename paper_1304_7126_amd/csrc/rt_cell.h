@@ -518,10 +518,10 @@ constexpr int QV_SMOOTH = QV_GRID + 6;
 #define RT_TAIL_CHUNK 64
 #endif
 constexpr unsigned TAIL_CHUNK = RT_TAIL_CHUNK;
-// positions a wave of the one-pass chemistry reserves at a time once past
-// the long chains (measured at 256^3 x 3: 64 -> 4.73 ms, 128 -> 4.30,
-// 256 -> 4.27, 512 -> 4.29, 1024 -> 5.54 ms, the last from the imbalance
-// at the end)
+// the most positions a wave of the one-pass chemistry reserves at a time
+// once past the long chains (measured at 256^3 x 3: 64 -> 4.73 ms, 128 ->
+// 4.30, 256 -> 4.27, 512 -> 4.29, 1024 -> 5.54 ms, the last from the
+// imbalance at the end); smaller grids take less (chem_sweep_chunk)
 #ifndef RT_CHEM_SWEEP_CHUNK
 #define RT_CHEM_SWEEP_CHUNK 256
 #endif

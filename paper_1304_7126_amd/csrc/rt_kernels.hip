@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_long_list(uint8_t *__restrict__ prev, s
 // lane whose cell is done no longer idles until its wave's other lanes are.
 template <typename R, int M, int V>
 __global__ __launch_bounds__(256, 3) void k_chem_all(const KChem *__restrict__ kp, double dt, ChemIO<R> io, QueueView q,
-                                                     DevStats *__restrict__ st)
+                                                     unsigned sweep_chunk, DevStats *__restrict__ st)
 {
     const KChem &k = *kp;
     constexpr bool SM = (V & V_SMOOTH) != 0;
@@ -581,10 +581,10 @@ __global__ __launch_bounds__(256, 3) void k_chem_all(const KChem *__restrict__ k
                 } else {
                     // one wave's width at a time among the long chains, so
                     // that a wave does not hold a second set of them; more
-                    // in the sweep, where each reservation is an atomic on
-                    // the one counter every wave shares
+                    // in the sweep (sweep_chunk), where each reservation is
+                    // an atomic on the one counter every wave shares
                     const unsigned more = nneed - ravail;
-                    const unsigned chunk = rbase < nl ? TAIL_CHUNK : CHEM_SWEEP_CHUNK;
+                    const unsigned chunk = rbase < nl ? TAIL_CHUNK : sweep_chunk;
                     const unsigned take = more > chunk ? more : chunk;
                     const int leader = __ffsll((long long)m) - 1;
                     unsigned base = 0;
@@ -721,6 +721,16 @@ hipError_t launch_chem(int part, bool fp32, const KGrid &g, const KChem &kc, con
     return hipGetLastError();
 }
 
+// Positions a wave reserves at a time in the sweep: a quarter of a wave's
+// share of the grid, between one wave's width and CHEM_SWEEP_CHUNK (on a
+// small grid large reservations would leave the work to a few waves).
+static unsigned chem_sweep_chunk(size_t ncell)
+{
+    const size_t share = ncell / ((size_t)CHEM_ALL_BLOCKS * 4) / 4;
+    const size_t c = share < TAIL_CHUNK ? TAIL_CHUNK : (share > CHEM_SWEEP_CHUNK ? CHEM_SWEEP_CHUNK : share);
+    return (unsigned)c;
+}
+
 // one-pass chemistry: queue counters reset, the list of long chains, then
 // the persistent kernel
 template <typename R, int M, int V>
@@ -731,7 +741,8 @@ static void launch_all(const KChem *dk, double dt, const ChemIO<R> &io, const Qu
     if (io.prev_att && io.ncell > 0)
         hipLaunchKernelGGL(k_long_list, dim3((unsigned)((io.ncell + 1023) / 1024)), dim3(256), 0, s, io.prev_att,
                            io.ncell, q.cell, q.cap, q.cnt[0]);
-    hipLaunchKernelGGL((k_chem_all<R, M, V>), dim3(CHEM_ALL_BLOCKS), dim3(256), 0, s, dk, dt, io, q, st);
+    hipLaunchKernelGGL((k_chem_all<R, M, V>), dim3(CHEM_ALL_BLOCKS), dim3(256), 0, s, dk, dt, io, q,
+                       chem_sweep_chunk(io.ncell), st);
 }
 
 template <typename R, int V>
