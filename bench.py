@@ -250,6 +250,8 @@ def bench_shadow(args):
     st = ri.initial_state(w)
     ctx = RTContext.for_workload(w)
     ctx.load_state(st)
+    ctx.set_chem_path(args.chem_path)
+    ctx.set_transport_path(args.transport_path)
     inside = st["nH"] > 1e-3
     del st
     dt = ctx.courant_dt()
@@ -519,7 +521,7 @@ def field_errors(a, b, M):
     return out
 
 
-def timed_config(w, fp32, steps, warmup, ijk, nd, st=None, acct=False):
+def timed_config(w, fp32, steps, warmup, ijk, nd, st=None, acct=False, chem_path="auto", path="auto"):
     """Run a workload on the GPU: `warmup` steps, back to the initial state,
     then `steps` timed rt_step calls.  Returns (context, ms per step, per-step
     series, stats)."""
@@ -531,6 +533,8 @@ def timed_config(w, fp32, steps, warmup, ijk, nd, st=None, acct=False):
     ctx = RTContext.for_workload(w, fp32=fp32)
     ctx.load_state(st)
     ctx.set_sources(ijk, ctx.source_rates(nd))
+    ctx.set_chem_path(chem_path)
+    ctx.set_transport_path(path)
     dt = ctx.courant_dt()
     if warmup > 0:
         ctx.step(dt, warmup)
@@ -598,7 +602,8 @@ def bench_stromgren(args):
     steps = args.steps
     w = ri.stromgren_32(steps)
     ijk, nd = ri.workload_sources(w)
-    ctx, dt, ms, series, s = timed_config(w, False, steps, args.warmup, ijk, nd)
+    ctx, dt, ms, series, s = timed_config(w, False, steps, args.warmup, ijk, nd, chem_path=args.chem_path,
+                                          path=args.transport_path)
     g = ctx.state_numpy()
     nH = w.nH_mean
     alpha_B = 2.59e-13
@@ -628,7 +633,8 @@ def bench_plain128(args):
     steps = 200 if args.steps == 100 else args.steps
     w = ri.lognormal_128(steps)
     ijk, nd = ri.random_sources(w.n, w.n_sources, w.seed)
-    ctx, dt, ms, series, s = timed_config(w, False, steps, args.warmup, ijk, nd)
+    ctx, dt, ms, series, s = timed_config(w, False, steps, args.warmup, ijk, nd, chem_path=args.chem_path,
+                                          path=args.transport_path)
     print(json.dumps(line("RT cell-group updates/s, 128^3 x 3 groups (FP64, HLL, 50 sources)",
                           w.ncell * 3 / (ms * 1e-3), "cell-group updates/s", steps, args.warmup, ms, "f64",
                           "lognormal 128^3 x 3 groups, 6.6 kpc, sigma_ln 1, mean n_H 1e-3, 50 sources, HLL, "

@@ -792,6 +792,21 @@ static SmoothArgs smooth_args(const rt_ctx *c, int pre_set, bool injected)
     return a;
 }
 
+// One pass or two for the chemistry after a separate transport.  Measured
+// on the lognormal workload (mixed precision, steps 1-40, ms per step, one
+// pass / two passes): 96^3 1.27 / 0.97, 128^3 1.57 / 1.34, 160^3 2.15 /
+// 2.14, 192^3 2.70 / 2.82, 224^3 3.95 / 4.53, 256^3 5.42 / 5.97.  On small
+// grids the lockstep head pass, with many more waves in flight, hides the
+// latency of taking cells better than the persistent lanes do.
+constexpr size_t CHEM_ONE_PASS_MIN_CELLS = 5000000;
+
+static bool use_one_pass(const rt_ctx *c)
+{
+    if (c->chem_path == RT_CHEM_ONE_PASS) return true;
+    if (c->chem_path == RT_CHEM_TWO_PASS) return false;
+    return c->grid.ncell >= CHEM_ONE_PASS_MIN_CELLS;
+}
+
 static rt_status do_chem(rt_ctx *c, double dt)
 {
     SmoothArgs sa;
@@ -815,7 +830,7 @@ static rt_status do_chem(rt_ctx *c, double dt)
         if (r != RT_OK) return r;
     }
     unsigned long long *hist = c->acct ? c->dstats->hist : nullptr;
-    if (c->chem_path != RT_CHEM_TWO_PASS) {
+    if (use_one_pass(c)) {
         rt_status r = timed(c, TM_HEAD, [&]() -> rt_status {
             RT_HIP(c, launch_chem_all(c->fp32, c->grid, c->kchem, c->dkchem, dt, c->st.N[c->cur], c->st.F[c->cur],
                                       c->st.xHII, c->st.xHeII, c->st.xHeIII, c->st.T, c->st.nH, c->st.nacc,
