@@ -120,8 +120,8 @@ __device__ __forceinline__ Dual dexp(const Dual &a)
     const double e = exp(a.v);
     return dchain(a, e, e);
 }
-__device__ __forceinline__ Dual dlog(const Dual &a) { return dchain(a, log(a.v), 1.0 / a.v); }
-__device__ __forceinline__ Dual dlog1p(const Dual &a) { return dchain(a, log1p(a.v), 1.0 / (1.0 + a.v)); }
+__device__ __forceinline__ Dual dlog(const Dual &a) { return dchain(a, rt_log(a.v), 1.0 / a.v); }
+__device__ __forceinline__ Dual dlog1p(const Dual &a) { return dchain(a, rt_log1p(a.v), 1.0 / (1.0 + a.v)); }
 __device__ __forceinline__ Dual dsqrt(const Dual &a)
 {
     const double s = sqrt(a.v);
@@ -132,8 +132,8 @@ __device__ __forceinline__ Dual dsqrt(const Dual &a)
 __device__ __forceinline__ double val(double a) { return a; }
 __device__ __forceinline__ double val(const Dual &a) { return a.v; }
 __device__ __forceinline__ double dexp(double a) { return exp(a); }
-__device__ __forceinline__ double dlog(double a) { return log(a); }
-__device__ __forceinline__ double dlog1p(double a) { return log1p(a); }
+__device__ __forceinline__ double dlog(double a) { return rt_log(a); }
+__device__ __forceinline__ double dlog1p(double a) { return rt_log1p(a); }
 __device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
 template <class D>
 __device__ __forceinline__ D cst(double v);

@@ -2,13 +2,16 @@
 //
 // Closure (Sec. 2, eqs. edd2/eddTens/Udir), intercell fluxes (Sec. 3.2,
 // eqs. glf/hll) and the App. E rate coefficients with their T-derivatives.
-// Rates are evaluated from one log(T), sqrt(T) and 1/T per temperature:
+// Rates are evaluated from one ln T, sqrt(T) and 1/T per temperature:
 // powers become exp(p ln lambda), the Hui & Gnedin denominators
-// exp(-r log1p((lambda/l0)^q)), and derivatives come from logarithmic
-// derivatives (dv/dT = v/T * dln v/dln T).
+// exp(-r ln(1 + (lambda/l0)^q)), and derivatives come from logarithmic
+// derivatives (dv/dT = v/T * dln v/dln T).  The logarithms are those of
+// rt_math.h.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "rt_math.h"
 
 // Multiplies and adds are fused into FMAs only where they form one source
 // expression (a * b + c): the front end marks exactly those, and the
@@ -216,7 +219,7 @@ __device__ __forceinline__ Tq make_Tq(double T)
 {
     Tq q;
     q.T = T;
-    q.lnT = log(T);
+    q.lnT = rt_log(T);
     q.invT = 1.0 / T;
     q.sqT = sqrt(T);
     q.s5 = q.sqT * 3.1622776601683795e-3;  // sqrt(1e-5)
@@ -241,7 +244,7 @@ __device__ __forceinline__ vd r_hg(const Tq &q, double A, double lnTL, double p,
     const double lnlam = lnTL - q.lnT;
     const double u = exp(qq * (lnlam - lnl0));
     vd o;
-    o.v = A * exp(p * lnlam - r * log1p(u));
+    o.v = A * exp(p * lnlam - r * rt_log1p(u));
     const double dlnlam = p - r * qq * u / (1.0 + u);  // dln v / dln lam
     o.d = -o.v * dlnlam * q.invT;
     return o;
@@ -254,7 +257,7 @@ __device__ __forceinline__ vd r_hgc(const Tq &q, double B, double lnTL, double p
     const double lnlam = lnTL - q.lnT;
     const double u = exp(qq * (lnlam - lnl0));
     vd o;
-    o.v = B * q.T * exp(p * lnlam - r * log1p(u));
+    o.v = B * q.T * exp(p * lnlam - r * rt_log1p(u));
     const double dlnlam = p - r * qq * u / (1.0 + u);
     o.d = o.v * (1.0 - dlnlam) * q.invT;
     return o;
@@ -351,8 +354,8 @@ __device__ __forceinline__ void cooling(const Tq &q, double a_exp, double ne, do
         const double l1 = LN_TL_HI - q.lnT, l3 = LN_TL_HEII - q.lnT;
         const double u1 = exp(qq * (l1 - lnl0));
         const double u3 = u1 * ratio;
-        eHII.v = B * q.T * exp(p * l1 - r * log1p(u1));
-        eHeIII.v = 8.0 * B * q.T * exp(p * l3 - r * log1p(u3));
+        eHII.v = B * q.T * exp(p * l1 - r * rt_log1p(u1));
+        eHeIII.v = 8.0 * B * q.T * exp(p * l3 - r * rt_log1p(u3));
         eHII.d = eHII.v * (1.0 - (p - r * qq * u1 / (1.0 + u1))) * q.invT;
         eHeIII.d = eHeIII.v * (1.0 - (p - r * qq * u3 / (1.0 + u3))) * q.invT;
     }
