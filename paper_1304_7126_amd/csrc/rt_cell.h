@@ -336,9 +336,20 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
     for (int g = 0; g < M; ++g) D[g] = k.csN[g][0] * nHI + k.csN[g][1] * nHeI + k.csN[g][2] * nHeII;
     for (;;) {
         bool fail = false;
+        if constexpr (M == 3) {
+            // the three absorption factors 1/(1 + h D_g) from one division
+            const double a0 = 1.0 + h * D[0], a1 = 1.0 + h * D[1], a2 = 1.0 + h * D[2];
+            const double a12 = a1 * a2;
+            const double ia = 1.0 / (a0 * a12);
+            rd[0] = ia * a12;
+            rd[1] = ia * (a0 * a2);
+            rd[2] = ia * (a0 * a1);
+        } else {
+#pragma unroll
+            for (int g = 0; g < M; ++g) rd[g] = 1.0 / (1.0 + h * D[g]);
+        }
 #pragma unroll
         for (int g = 0; g < M; ++g) {
-            rd[g] = 1.0 / (1.0 + h * D[g]);
             if constexpr (SM) {
                 // a negative rate may take the update below zero: it stops there
                 const double src = CA ? Crec[g] + s.Nr[g] : s.Nr[g];

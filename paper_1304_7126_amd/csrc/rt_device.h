@@ -215,13 +215,32 @@ struct Tq {
     double T, lnT, invT, sqT, s5, g;  // sqT = sqrt(T), s5 = sqrt(T/1e5), g = 1/(1+s5)
 };
 
+// sqrt(T) and 1/T (T > 0 finite) from the hardware reciprocal square root
+// r: g = T r and h = r/2 approach sqrt(T) and 1/(2 sqrt(T)); one Goldschmidt
+// step on both, then a Newton correction of g from its residual T - g^2 and
+// one more step on h, leave each within an ulp, and 1/T = (2h)^2.
+__device__ __forceinline__ void sqrt_and_inv(double T, double &sq, double &inv)
+{
+    const double r = __builtin_amdgcn_rsq(T);
+    double g = T * r, h = 0.5 * r;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, T);
+    g = fma(d, h, g);
+    const double e2 = fma(-g, h, 0.5);
+    h = fma(h, e2, h);
+    const double h2 = h + h;
+    sq = g;
+    inv = h2 * h2;
+}
+
 __device__ __forceinline__ Tq make_Tq(double T)
 {
     Tq q;
     q.T = T;
     q.lnT = rt_log(T);
-    q.invT = 1.0 / T;
-    q.sqT = sqrt(T);
+    sqrt_and_inv(T, q.sqT, q.invT);
     q.s5 = q.sqT * 3.1622776601683795e-3;  // sqrt(1e-5)
     q.g = 1.0 / (1.0 + q.s5);
     return q;
