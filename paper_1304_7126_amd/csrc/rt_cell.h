@@ -205,7 +205,7 @@ __device__ __forceinline__ U4<R> transport_cell(const Nbr &nb, uint32_t i, size_
 // --------------------------------------------------------- thermochemistry
 __device__ __forceinline__ double mu_of(const KChem &k, double x, double y2, double y3)
 {
-    return 1.0 / (k.X * (1.0 + x) + 0.25 * k.Y * (1.0 + y2 + 2.0 * y3));
+    return rcp_pos(k.X * (1.0 + x) + 0.25 * k.Y * (1.0 + y2 + 2.0 * y3));
 }
 
 // |a - b| > f b for b > 0: the relative-change test of App. A without a division
@@ -453,13 +453,13 @@ __device__ __forceinline__ bool chem_attempt(const KChem &k, const CC &cc, St &s
         const Tq q2 = make_Tq(iso ? cc.Tiso : Tmun * mu_of(k, xn, y2, y3));
         const vd bHe1 = beta_HeI(q2), aHe2 = alpha_HeII<CA>(q2), bHe2 = beta_HeII(q2), aHe3 = alpha_HeIII<CA>(q2);
         const double y1 = 1.0 - y2 - y3;
-        const double y1n = (y1 + y2 * aHe2.v * ne1 * h) / (1.0 + (bHe1.v * ne1 + GHeI) * h);
-        y2n = (y2 + (y1n * (bHe1.v * ne1 + GHeI) + y3 * aHe3.v * ne1) * h) /
-              (1.0 + ((bHe2.v + aHe2.v) * ne1 + GHeII) * h);
+        const double y1n = div_pos(y1 + y2 * aHe2.v * ne1 * h, 1.0 + (bHe1.v * ne1 + GHeI) * h);
+        y2n = div_pos(y2 + (y1n * (bHe1.v * ne1 + GHeI) + y3 * aHe3.v * ne1) * h,
+                      1.0 + ((bHe2.v + aHe2.v) * ne1 + GHeII) * h);
         const double ne2 = xn * nH + (y2n + 2.0 * y3) * nHe;
         const Tq q3 = make_Tq(iso ? cc.Tiso : Tmun * mu_of(k, xn, y2n, y3));
         const vd bHe2b = beta_HeII(q3), aHe3b = alpha_HeIII<CA>(q3);
-        y3n = (y3 + y2n * (bHe2b.v * ne2 + GHeII) * h) / (1.0 + aHe3b.v * ne2 * h);
+        y3n = div_pos(y3 + y2n * (bHe2b.v * ne2 + GHeII) * h, 1.0 + aHe3b.v * ne2 * h);
         const double S = y1n + y2n + y3n;
         if (!(y1n >= y2n && y1n >= y3n)) {
             if (y2n >= y3n) y2n -= (S - 1.0);

@@ -36,6 +36,27 @@ constexpr double EPS_HEII = 54.42 * EVERG;
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 
+// FP64 reciprocal and quotient for a denominator b >= 1/2 (finite), as the
+// rate coefficients and the helium updates have: the hardware reciprocal
+// refined by two Newton steps (within an ulp), and for the quotient one
+// correction from its residual.  The IEEE division's range scaling and
+// special-case fix-ups are not needed there.
+__device__ __forceinline__ double rcp_pos(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double div_pos(double a, double b)
+{
+    const double r = rcp_pos(b);
+    const double q = a * r;
+    const double rem = fma(-b, q, a);
+    return fma(rem, r, q);
+}
+
 // ---------------------------------------------------------------------
 // M1 pressure flux.  For a cell state U = (N, F) the physical flux along
 // axis d is G_d = (F_d, c^2 P_d.), P = N D with
@@ -242,7 +263,7 @@ __device__ __forceinline__ Tq make_Tq(double T)
     q.lnT = rt_log(T);
     sqrt_and_inv(T, q.sqT, q.invT);
     q.s5 = q.sqT * 3.1622776601683795e-3;  // sqrt(1e-5)
-    q.g = 1.0 / (1.0 + q.s5);
+    q.g = rcp_pos(1.0 + q.s5);
     return q;
 }
 
@@ -264,7 +285,7 @@ __device__ __forceinline__ vd r_hg(const Tq &q, double A, double lnTL, double p,
     const double u = exp(qq * (lnlam - lnl0));
     vd o;
     o.v = A * exp(p * lnlam - r * rt_log1p(u));
-    const double dlnlam = p - r * qq * u / (1.0 + u);  // dln v / dln lam
+    const double dlnlam = p - r * qq * div_pos(u, 1.0 + u);  // dln v / dln lam
     o.d = -o.v * dlnlam * q.invT;
     return o;
 }
@@ -277,7 +298,7 @@ __device__ __forceinline__ vd r_hgc(const Tq &q, double B, double lnTL, double p
     const double u = exp(qq * (lnlam - lnl0));
     vd o;
     o.v = B * q.T * exp(p * lnlam - r * rt_log1p(u));
-    const double dlnlam = p - r * qq * u / (1.0 + u);
+    const double dlnlam = p - r * qq * div_pos(u, 1.0 + u);
     o.d = o.v * (1.0 - dlnlam) * q.invT;
     return o;
 }
@@ -375,8 +396,8 @@ __device__ __forceinline__ void cooling(const Tq &q, double a_exp, double ne, do
         const double u3 = u1 * ratio;
         eHII.v = B * q.T * exp(p * l1 - r * rt_log1p(u1));
         eHeIII.v = 8.0 * B * q.T * exp(p * l3 - r * rt_log1p(u3));
-        eHII.d = eHII.v * (1.0 - (p - r * qq * u1 / (1.0 + u1))) * q.invT;
-        eHeIII.d = eHeIII.v * (1.0 - (p - r * qq * u3 / (1.0 + u3))) * q.invT;
+        eHII.d = eHII.v * (1.0 - (p - r * qq * div_pos(u1, 1.0 + u1))) * q.invT;
+        eHeIII.d = eHeIII.v * (1.0 - (p - r * qq * div_pos(u3, 1.0 + u3))) * q.invT;
     }
     // eta_HeII = k_B T alpha_HeII
     constexpr double pHe2 = CA ? 0.654 : 0.75;
@@ -385,7 +406,7 @@ __device__ __forceinline__ void cooling(const Tq &q, double a_exp, double ne, do
     // dielectronic recombination
     const double ed2 = exp(-94000.0 * q.invT);
     const double om = 1.24e-13 * exp(-1.5 * q.lnT - 470000.0 * q.invT) * (1.0 + 0.3 * ed2);
-    const double oml = -1.5 + 470000.0 * q.invT + 0.3 * ed2 * 94000.0 * q.invT / (1.0 + 0.3 * ed2);
+    const double oml = -1.5 + 470000.0 * q.invT + div_pos(0.3 * ed2 * 94000.0 * q.invT, 1.0 + 0.3 * ed2);
     // bremsstrahlung and Compton
     const double th = 1.42e-27 * sqT;
     const double Tg = 2.727 / a_exp;
