@@ -12,7 +12,8 @@
 //   - LDS for the x- and y-faces: every thread publishes its state, the row
 //     of the pressure tensor and the speed pair along x and along y; the
 //     rows just outside the tile (y halo) are evaluated by the tile's edge
-//     threads.
+//     threads.  In FP32 with HLL fluxes the wave-speed table is read from
+//     an LDS copy.
 // Each x- and y-face flux is evaluated once, by the cell on its low side,
 // and reaches the cell on its high side through LDS.  The next plane's
 // state is loaded one iteration ahead of its use.  Every face flux is
@@ -198,22 +199,36 @@ __device__ __forceinline__ void block_sum2(double a, double b, double &sa, doubl
 // own cells.  acct (or null): per block of a group, the sum of the new N
 // and of the outward boundary flux of the group, at acct[6 b + grp] and
 // acct[6 b + 3 + grp] with b = blockIdx.x + gridDim.x * blockIdx.y.
-// The LDS records are double-buffered: a plane's records are written into
-// one buffer and read after one barrier; the next plane's go to the other
-// buffer, which every thread has finished reading once it passed that
-// barrier.  The face fluxes are written after the first barrier of a plane
-// and read after the second; the next plane writes them only after its
-// first barrier, which every thread reaches once it has read them.
+// Two barriers per plane: records are written before the first and read
+// between the two; face fluxes are written between the two and read after
+// the second.  A thread writes the next plane's records only after the
+// second barrier, when every thread has read this plane's, and its next
+// fluxes only after the next first barrier, when every thread has read
+// these: one buffer of each suffices.
 // AHEAD: the plane above and the halo rows are loaded one plane before
 // their use (more registers); otherwise at the start of their plane.
+// FP32 HLL: the wave-speed table (101 x 101 nodes of float pairs, 80 KiB)
+// is copied into LDS when the block starts, so that the twelve bilinear
+// corner reads of a cell (three axes) and those of the halo rows are LDS
+// reads instead of L2 gathers; with the single record buffer it fits the
+// 160 KiB a workgroup may hold.
+constexpr int LTAB_CAP = 101 * 101 * 2;
 template <typename R, int FLUX, int NT, bool AHEAD>
 __global__ __launch_bounds__(NT) void k_transport_z(KGrid g, int H, int zc, R c, R kdx, const R *__restrict__ Nin,
                                                     const R *__restrict__ Fin, R *__restrict__ Nout,
-                                                    R *__restrict__ Fout, const R *__restrict__ tab, int nf, int nth,
+                                                    R *__restrict__ Fout, const R *__restrict__ gtab, int nf, int nth,
                                                     double *__restrict__ acct)
 {
-    __shared__ R sh[2][XREC][NT];
+    constexpr bool LT = FLUX == 1 && sizeof(R) == 4;
+    __shared__ R sh[XREC][NT];
     __shared__ R shf[8][NT];  // the fluxes through each cell's +x and +y faces
+    __shared__ R stab[LT ? LTAB_CAP : 1];
+    const R *__restrict__ tab = gtab;
+    if constexpr (LT) {
+        for (int k = threadIdx.x; k < nf * nth * 2; k += blockDim.x) stab[k] = gtab[k];
+        __syncthreads();
+        tab = stab;
+    }
     const int grp = blockIdx.z;
     const int t = threadIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -264,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_transport_z(KGrid g, int H, int zc, R c,
     }
 
     for (int z = z0; z < z1; ++z) {
-        R(*buf)[NT] = sh[(z - z0) & 1];
+        R(*buf)[NT] = sh;
         // loads for the next plane, in flight during this one
         U4<R> pre_u, pre_dn, pre_up;
         const bool more = z + 1 < z1;
@@ -461,7 +476,8 @@ hipError_t launch_transport_z(bool fp32, int flux, const KGrid &g, int M, double
                               const void *Fin, void *Nout, void *Fout, const void *hll, int nf, int nth, double *acct,
                               hipStream_t s)
 {
-    if (!transport_z_fits(fp32, g)) return hipErrorInvalidValue;
+    // the FP32 HLL kernel holds the table in LDS (rt_init builds 101 x 101)
+    if (!transport_z_fits(fp32, g) || (fp32 && flux && nf * nth * 2 > LTAB_CAP)) return hipErrorInvalidValue;
     const double kdx = dt / g.dx;
     return fp32 ? launch_z<float>(flux, g, M, c, kdx, Nin, Fin, Nout, Fout, hll, nf, nth, acct, s)
                 : launch_z<double>(flux, g, M, c, kdx, Nin, Fin, Nout, Fout, hll, nf, nth, acct, s);
