@@ -631,19 +631,21 @@ constexpr uint8_t ATT_MASK = 0x7F, ATT_LISTED = 0x80;
 
 // Write a finished cell: N, the flux in the destination scaled by fs (with
 // smoothed RT: fs F^t + fb (F' - F^t)/dt_RT), the gas state and the counters.
-// The fluxes it rescales are loaded before anything is written: a load
-// issued after a store waits for that store (one counter tracks both), so
-// loads placed between the stores would each wait out the stores before
-// them.
-template <typename R, int M, class S>
-__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const S &s, double T, uint8_t mark = 0)
+// The destination fluxes (fp) are in hand before anything is written, given
+// by the caller (LOADED) or loaded first: a load issued after a store waits
+// for that store (one counter tracks both), so loads placed between the
+// stores would each wait out the stores before them.
+template <typename R, int M, bool LOADED, class S>
+__device__ __forceinline__ void store_cell_impl(const ChemIO<R> &io, uint32_t i, const S &s, double T,
+                                                const R *fpin, uint8_t mark)
 {
     constexpr bool SM = std::is_same<S, CSR>::value;
     const size_t nc = io.ncell;
     R fp[3 * M], ft[3 * M];
 #pragma unroll
     for (int j = 0; j < 3 * M; ++j) {
-        fp[j] = io.F[(size_t)j * nc + i];
+        if constexpr (LOADED) fp[j] = fpin[j];
+        else fp[j] = io.F[(size_t)j * nc + i];
         if constexpr (SM) ft[j] = io.sm.F[(size_t)j * nc + i];
         else ft[j] = fp[j];
     }
@@ -660,6 +662,20 @@ __device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, cons
     for (int g = 0; g < M; ++g)
 #pragma unroll
         for (int d = 0; d < 3; ++d) io.F[(size_t)(3 * g + d) * nc + i] = finish_flux(io, s, g, fp[3 * g + d], ft[3 * g + d]);
+}
+
+template <typename R, int M, class S>
+__device__ __forceinline__ void store_cell(const ChemIO<R> &io, uint32_t i, const S &s, double T, uint8_t mark = 0)
+{
+    store_cell_impl<R, M, false>(io, i, s, T, nullptr, mark);
+}
+
+// the same with the destination fluxes loaded by the caller
+template <typename R, int M, class S>
+__device__ __forceinline__ void store_cell_with(const ChemIO<R> &io, uint32_t i, const S &s, double T, const R *fp,
+                                                uint8_t mark = 0)
+{
+    store_cell_impl<R, M, true>(io, i, s, T, fp, mark);
 }
 
 }  // namespace rtm1

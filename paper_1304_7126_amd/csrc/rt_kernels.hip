@@ -359,6 +359,9 @@ __global__ __launch_bounds__(256, 3) void k_tail(const KChem *__restrict__ kp, C
     const unsigned n1 = min(*q.cnt[1], q.rlen[1]);
     const unsigned n = n0 + n1 + min(*q.cnt[2], q.rlen[2]);
     std::conditional_t<(V & V_SMOOTH) != 0, CSR, CS> s;
+    // the cell's destination fluxes, loaded with the cell (as in k_chem_all)
+    constexpr bool PRE = (V & V_SMOOTH) == 0;
+    R fpre[PRE ? 3 * M : 1];
     uint32_t cell = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
@@ -399,6 +402,10 @@ __global__ __launch_bounds__(256, 3) void k_tail(const KChem *__restrict__ kp, C
                 if (need && t < n) {
                     const unsigned pos = t < n0 ? t : (t < n0 + n1 ? q.rbeg[1] + (t - n0) : q.rbeg[2] + (t - n0 - n1));
                     cell = q_load(k, q, pos, s, cc);
+                    if constexpr (PRE) {
+#pragma unroll
+                        for (int j = 0; j < 3 * M; ++j) fpre[j] = io.F[(size_t)j * io.ncell + cell];
+                    }
                     active = true;
                     first = t < n0;
                 }
@@ -414,7 +421,8 @@ __global__ __launch_bounds__(256, 3) void k_tail(const KChem *__restrict__ kp, C
         if (active) {
             if (chem_attempt<CM, V>(k, cc, s, fl)) {
                 const double T = chem_finish<CM>(k, cc, s, fl);
-                store_cell<R, M>(io, cell, s, T);
+                if constexpr (PRE) store_cell_with<R, M>(io, cell, s, T, fpre);
+                else store_cell<R, M>(io, cell, s, T);
                 if (io.hist) hist_add(s_hist, s.acc);
                 a_acc += (unsigned long long)s.acc;
                 a_att += (unsigned long long)s.att;
@@ -503,6 +511,10 @@ __global__ __launch_bounds__(256, 3) void k_chem_all(const KChem *__restrict__ k
     const unsigned nl = io.prev_att ? min(*q.cnt[0], q.cap) : 0u;
     const unsigned n = nl + (unsigned)nc;
     std::conditional_t<SM, CSR, CS> s;
+    // the cell's destination fluxes, loaded with the cell (not with smoothed
+    // RT, whose larger state leaves no registers for them)
+    constexpr bool PRE = !SM;
+    R fpre[PRE ? 3 * M : 1];
     uint32_t cell = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false, raised = false;
@@ -540,26 +552,31 @@ __global__ __launch_bounds__(256, 3) void k_chem_all(const KChem *__restrict__ k
         s.y2 = io.xHeII[i];
         s.y3 = io.xHeIII[i];
         cc = make_cc(k, io.nH[i] * io.ia3, io.T[i]);
+        // the fluxes are needed only when the cell is written: loaded now,
+        // they arrive while the attempts run instead of stalling the wave
+        // at the write
+        if constexpr (PRE) {
+#pragma unroll
+            for (int j = 0; j < 3 * M; ++j) fpre[j] = io.F[(size_t)j * nc + i];
+        }
         return chem_init<CM, V>(k, dt, cc.Tiso, fin, s);
     };
     // write a cell whose chemistry has ended.  Its fluxes are checked here,
-    // where they are read anyway: a non-finite one means the cell is
-    // written back as loaded (what the head pass does when it finds one
-    // before the chemistry), and the flags of the discarded attempts are
-    // dropped
+    // where they are used: a non-finite one means the cell is written back
+    // as loaded (what the head pass does when it finds one before the
+    // chemistry), and the flags of the discarded attempts are dropped
     auto finish = [&]() {
         bool fin = true;
 #pragma unroll
-        for (int grp = 0; grp < M; ++grp)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) fin = fin && isfinite(io.F[(size_t)(3 * grp + d) * nc + cell]);
+        for (int j = 0; j < 3 * M; ++j) fin = fin && isfinite(PRE ? fpre[j] : io.F[(size_t)j * nc + cell]);
         if (!fin) {
             load(cell, false);
             cfl = 2u;
         }
         fl |= cfl;
         const double T = chem_finish<CM>(k, cc, s, fl);
-        store_cell<R, M>(io, cell, s, T, mark);
+        if constexpr (PRE) store_cell_with<R, M>(io, cell, s, T, fpre, mark);
+        else store_cell<R, M>(io, cell, s, T, mark);
         if (io.hist) hist_add(s_hist, s.acc);
         a_acc += (unsigned long long)s.acc;
         a_att += (unsigned long long)s.att;
