@@ -288,7 +288,7 @@ rt_status rt_set_transport_path(rt_ctx *ctx, int path);
 /* Kernel arrangement of the chemistry that follows a separate transport
  * (rt_thermochem, and rt_step on the z-marching path; App. A); results are
  * the same bits on every path:
- *   RT_CHEM_AUTO      one pass on grids of 5,000,000 cells or more, two
+ *   RT_CHEM_AUTO      one pass on grids of 2,000,000 cells or more, two
  *                     passes on smaller ones (the faster of the two there)
  *   RT_CHEM_TWO_PASS  a head pass of head_attempts attempts per cell in
  *                     lockstep, then the queued cells in a persistent tail

@@ -793,12 +793,15 @@ static SmoothArgs smooth_args(const rt_ctx *c, int pre_set, bool injected)
 }
 
 // One pass or two for the chemistry after a separate transport.  Measured
-// on the lognormal workload (mixed precision, steps 1-40, ms per step, one
-// pass / two passes): 96^3 1.27 / 0.97, 128^3 1.57 / 1.34, 160^3 2.15 /
-// 2.14, 192^3 2.70 / 2.82, 224^3 3.95 / 4.53, 256^3 5.42 / 5.97.  On small
-// grids the lockstep head pass, with many more waves in flight, hides the
-// latency of taking cells better than the persistent lanes do.
-constexpr size_t CHEM_ONE_PASS_MIN_CELLS = 5000000;
+// on the lognormal workload (mixed precision, n/256 x 200 sources, steps
+// 1-40, ms per step, one pass / two passes): 96^3 1.00 / 0.85, 128^3 1.30 /
+// 1.19, 160^3 1.76 / 1.90, 192^3 2.16 / 2.51, 224^3 3.17 / 3.97; at 128^3
+// with more I-front cells the one pass is ahead (FP64, 50 sources, 200
+// steps: 1.18 / 1.24; the shadow test: 0.94 / 1.07).  On small grids the
+// lockstep head pass, with many more waves in flight, hides the latency of
+// taking cells better than the persistent lanes do; long chains favour the
+// one pass, which starts them first.
+constexpr size_t CHEM_ONE_PASS_MIN_CELLS = 2000000;
 
 static bool use_one_pass(const rt_ctx *c)
 {
