@@ -116,20 +116,21 @@ __device__ __forceinline__ void bq_load(const BQueue &q, unsigned stride, uint32
     s.h = v[11 * c];
 }
 
-// write the finished state of a cell of a box with M groups (runtime M); the
-// transported flux in the destination is rescaled by fs
+// write the finished state of a cell of a box with M groups (runtime M);
+// fp holds the transported flux (in hand, so that no load sits between the
+// stores), written rescaled by fs
 template <typename R>
-__device__ __forceinline__ void bstore(const BoxDev &b, int dst, uint32_t i, const CS &s, double T)
+__device__ __forceinline__ void bstore(const BoxDev &b, int dst, uint32_t i, const CS &s, double T, const R *fp)
 {
     const size_t nc = b.g.ncell;
     R *N = (R *)b.N[dst];
     R *F = (R *)b.F[dst];
-    for (int g = 0; g < b.M; ++g) {
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        if (g >= b.M) break;
         N[(size_t)g * nc + i] = (R)s.N[g];
-        for (int d = 0; d < 3; ++d) {
-            R &f = F[(size_t)(3 * g + d) * nc + i];
-            f = (R)((double)f * s.fs[g]);
-        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[(size_t)(3 * g + d) * nc + i] = (R)((double)fp[3 * g + d] * s.fs[g]);
     }
     b.xHII[i] = s.x;
     b.xHeII[i] = s.y2;
@@ -174,6 +175,9 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
     CS s;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool done = true;
+    // the transported flux stays in registers: a queued cell's goes to the
+    // destination for the tail, a finished cell's is written once, rescaled
+    R fo[3 * M];
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
         s.N[g] = 0.0;
@@ -185,7 +189,6 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
         const Nbr nb = neighbours(b.g, i, ix, iy, iz);
         const R *Nin = (const R *)b.N[src];
         const R *Fin = (const R *)b.F[src];
-        R *Fout = (R *)b.F[1 - src];
         bool fin = true;
 #pragma unroll
         for (int grp = 0; grp < M; ++grp) {
@@ -193,9 +196,9 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
             const U4<R> o = transport_cell<R, FLUX>(nb, i, nc, Nin + (size_t)grp * nc, Fin + (size_t)3 * grp * nc, c,
                                                     (R)b.kdx, tab, nf, nth, bout, b.g, grp);
             s.N[grp] = (double)o.n;
-            Fout[(size_t)(3 * grp) * nc + i] = o.fx;
-            Fout[(size_t)(3 * grp + 1) * nc + i] = o.fy;
-            Fout[(size_t)(3 * grp + 2) * nc + i] = o.fz;
+            fo[3 * grp] = o.fx;
+            fo[3 * grp + 1] = o.fy;
+            fo[3 * grp + 2] = o.fz;
             fin = fin && isfinite(o.fx) && isfinite(o.fy) && isfinite(o.fz);
         }
         s.x = b.xHII[i];
@@ -221,6 +224,9 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
             const unsigned p = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
             if (p < q.cap) {
                 bq_store(q, stride, p, box, i, s);
+                R *Fout = (R *)b.F[1 - src];
+#pragma unroll
+                for (int j = 0; j < 3 * M; ++j) Fout[(size_t)j * nc + i] = fo[j];
                 queued = true;
             }
         }
@@ -230,7 +236,7 @@ __device__ __forceinline__ void head_chunk(const BoxDev &b, uint32_t box, uint32
     }
     if (valid && !queued) {
         const double T = chem_finish<CM>(k, cc, s, fl);
-        bstore<R>(b, 1 - src, i, s, T);
+        bstore<R>(b, 1 - src, i, s, T, fo);
         a_acc += (unsigned long long)s.acc;
         a_att += (unsigned long long)s.att;
         a_max = a_max > (unsigned long long)s.att ? a_max : (unsigned long long)s.att;
@@ -302,6 +308,7 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
     const int lane = (int)(threadIdx.x & 63u);
     const unsigned n = min(q.ctr[1], q.cap);
     CS s;
+    R fpre[9];  // the cell's transported flux, loaded with the cell (used when it is written)
     uint32_t cell = 0, box = 0;
     CC cc{1.0, 0.0, 0.0, 0.0};
     bool active = false, exhausted = false;
@@ -335,7 +342,11 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
                 if (rbase >= n) exhausted = true;
                 if (need && p < n) {
                     bq_load(q, stride, p, box, cell, s);
-                    cc = make_cc(*boxes[box].kchem, boxes[box].nH[cell], boxes[box].T[cell]);
+                    const BoxDev &bb = boxes[box];
+                    cc = make_cc(*bb.kchem, bb.nH[cell], bb.T[cell]);
+                    const R *F = (const R *)bb.F[dst];
+#pragma unroll
+                    for (int j = 0; j < 9; ++j) fpre[j] = j < 3 * bb.M ? F[(size_t)j * bb.g.ncell + cell] : R(0);
                     active = true;
                 }
             }
@@ -345,7 +356,7 @@ __global__ __launch_bounds__(256) void k_btail(const BoxDev *__restrict__ boxes,
             const KChem &k = *boxes[box].kchem;
             if (chem_attempt<CM>(k, cc, s, fl)) {
                 const double T = chem_finish<CM>(k, cc, s, fl);
-                bstore<R>(boxes[box], dst, cell, s, T);
+                bstore<R>(boxes[box], dst, cell, s, T, fpre);
                 a_acc += (unsigned long long)s.acc;
                 a_att += (unsigned long long)s.att;
                 a_max = a_max > (unsigned long long)s.att ? a_max : (unsigned long long)s.att;
