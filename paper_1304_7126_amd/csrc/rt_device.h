@@ -236,10 +236,13 @@ struct Tq {
     double T, lnT, invT, sqT, s5, g;  // sqT = sqrt(T), s5 = sqrt(T/1e5), g = 1/(1+s5)
 };
 
-// sqrt(T) and 1/T (T > 0 finite) from the hardware reciprocal square root
-// r: g = T r and h = r/2 approach sqrt(T) and 1/(2 sqrt(T)); one Goldschmidt
-// step on both, then a Newton correction of g from its residual T - g^2 and
-// one more step on h, leave each within an ulp, and 1/T = (2h)^2.
+// sqrt(T) and 1/T from the hardware reciprocal square root r: g = T r and
+// h = r/2 approach sqrt(T) and 1/(2 sqrt(T)); one Goldschmidt step on both,
+// then a Newton correction of g from its residual T - g^2 and one more step
+// on h, leave each within an ulp, and 1/T = (2h)^2.  A temperature that is
+// not positive and finite (only an input can be: the 10 % rule keeps the
+// substeps' temperatures within 10 % of each other) takes the IEEE square
+// root and division, in a branch no wave enters otherwise.
 __device__ __forceinline__ void sqrt_and_inv(double T, double &sq, double &inv)
 {
     const double r = __builtin_amdgcn_rsq(T);
@@ -254,6 +257,10 @@ __device__ __forceinline__ void sqrt_and_inv(double T, double &sq, double &inv)
     const double h2 = h + h;
     sq = g;
     inv = h2 * h2;
+    if (!(T > 0.0 && T < INFINITY)) {
+        sq = sqrt(T);
+        inv = 1.0 / T;
+    }
 }
 
 __device__ __forceinline__ Tq make_Tq(double T)
