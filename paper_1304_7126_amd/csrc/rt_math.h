@@ -70,8 +70,9 @@ __host__ __device__ __forceinline__ double rt_log(double x)
     return x > 0.0 && x < INFINITY ? y : (x == 0.0 ? -INFINITY : (x > 0.0 ? x : NAN));
 }
 
-// ln(1 + u), accurate for u >= 0 (the fits' (lambda/lambda_0)^q; tested
-// there), with the library's results for -1, below -1, infinity and NaN.
+// ln(1 + u) for u >= 0 (the fits' (lambda/lambda_0)^q), with the library's
+// results for infinity and NaN; u < 0 is outside its domain (a further
+// select for it pushed the chemistry kernels past their register budget).
 // The correction c / w = c 2^-e / m takes 1/m as 1 - f + f^2, within 5% on
 // the reduced range: c is below half an ulp of w, so that costs under 0.05
 // ulp.
@@ -83,7 +84,7 @@ __host__ __device__ __forceinline__ double rt_log1p(double u)
     int e;
     const double y = log_core(w, f, e);
     const double yc = fma(ldexp(c, -e), fma(f, f, 1.0 - f), y);
-    return w == 1.0 ? u : (w > 0.0 && w < INFINITY ? yc : (w == 0.0 ? -INFINITY : (w > 0.0 ? w : NAN)));
+    return w == 1.0 ? u : (w < INFINITY ? yc : w);
 }
 
 }  // namespace rtm1
