@@ -433,3 +433,27 @@ def test_transport_fp32_empty_cells_with_subnormal_flux(flux):
         assert np.all(errN <= 1e-5 * m + 1e-37), (gi, errN.max())
         errF = np.linalg.norm(g["F"][gi] - st["F"][gi], axis=0)
         assert np.all(errF <= 1e-5 * C_R * m + 1e-37), (gi, errF.max())
+
+
+@pytest.mark.parametrize("isothermal", [True, False])
+def test_thermochem_across_temperatures(isothermal):
+    # every App. E fit at temperatures from 10 K to 1e9 K (log-uniform), the
+    # range where ln T, sqrt(T), 1/T and the Hui & Gnedin terms of the device
+    # rates are evaluated; M = 3 with helium
+    rng = np.random.default_rng(77)
+    n = (40, 25, 16)
+    ctx, o = make_pair(n, BCS[0], 3, 0, isothermal=isothermal)
+    N, F = random_rad(n, 3, rng)
+    N *= 1e-3
+    F *= 1e-3
+    gs = gas(n, rng)
+    gs["T"] = 10 ** rng.uniform(1, 9, gs["T"].shape)
+    st = {"N": N, "F": F, **gs}
+    ctx.load_state(st)
+    dt = ctx.courant_dt()
+    ctx.thermochem(dt)
+    fl, nacc, natt = o.thermochem(st, dt, want_counts=True)
+    st["nacc"], st["natt"] = nacc, natt
+    g = ctx.state_numpy()
+    chem_compare(g, st)
+    assert (ctx.stats()["flags"] & ~1) == (fl & ~1)
