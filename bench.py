@@ -27,10 +27,15 @@ VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 # rocprofv3 summaries of the headline command (profiles/, written by
 # paper_1304_7126_amd.profiling): kernel durations, HBM byte counters and
-# VALU counters of the first chemistry pass over the timed launches.  Their
-# figures are used only while the kernel sources hash as when they were taken.
+# VALU counters of the dominant kernels over the timed launches, one set per
+# launch window that is timed (the default 10 warmup + 100 steps: launches
+# 11-110; 5 + 20 steps: launches 6-25).  Their figures are used only while
+# the kernel sources hash as when they were taken, and only for the window
+# they cover.
 PROFILE = os.path.join(ROOT, "profiles", "k_chem_all_256cube_3grp")
 PROFILE_TRANSPORT = os.path.join(ROOT, "profiles", "k_transport_z_256cube_3grp")
+PROFILE_SETS = {PROFILE: [PROFILE, PROFILE + "_launches6to25"],
+                PROFILE_TRANSPORT: [PROFILE_TRANSPORT, PROFILE_TRANSPORT + "_launches6to25"]}
 
 
 def parse():
@@ -775,6 +780,11 @@ def kernel_roofline(name, bytes_per_launch, ms_live, prefix, window, default_con
     if not default_config:
         r["profile"] = "not the profiled configuration"
         return r
+    # the summary set taken over these launches, if there is one
+    for cand in PROFILE_SETS.get(prefix, [prefix]):
+        if profile_figures(cand + "_kernel_stats.md", window)[0] is not None:
+            prefix = cand
+            break
     st, why = profile_figures(prefix + "_kernel_stats.md", window)
     by, why_b = profile_figures(prefix + "_pmc_bytes.md", window)
     va, why_v = profile_figures(prefix + "_pmc_valu.md", window)

@@ -133,10 +133,26 @@ def test_bench_roofline_uses_current_profiles_and_ignores_stale_ones(tmp_path):
 
 def test_committed_profiles_parse():
     import bench
+    windows = {"": [11, 110], "_launches6to25": [6, 25]}
     for prefix in (bench.PROFILE, bench.PROFILE_TRANSPORT):
-        for kind in ("_kernel_stats.md", "_pmc_bytes.md", "_pmc_valu.md", "_pmc_mix.md"):
-            f = profiling.read_figures(prefix + kind)
-            assert f is not None, prefix + kind
-            assert f["window"] == [11, 110]
-            assert len(f["kernel_source_hash"]) == 16
-            json.dumps(f)
+        assert len(bench.PROFILE_SETS[prefix]) == len(windows)
+        for cand in bench.PROFILE_SETS[prefix]:
+            suffix = cand[len(prefix):]
+            for kind in ("_kernel_stats.md", "_pmc_bytes.md", "_pmc_valu.md", "_pmc_mix.md"):
+                f = profiling.read_figures(cand + kind)
+                assert f is not None, cand + kind
+                assert f["window"] == windows[suffix]
+                assert len(f["kernel_source_hash"]) == 16
+                json.dumps(f)
+
+
+def test_bench_picks_the_profile_set_of_its_window(tmp_path, monkeypatch):
+    import bench
+    prefix = str(tmp_path / "k_chem_all_x")
+    for p, win, us in ((prefix, [11, 110], 4000.0), (prefix + "_launches6to25", [6, 25], 3000.0)):
+        profiling._write(p + "_kernel_stats.md", "t", ["cmd"], "body", {"window": win, "avg_us": us})
+    monkeypatch.setitem(bench.PROFILE_SETS, prefix, [prefix, prefix + "_launches6to25"])
+    nbytes = 168 * 256 ** 3
+    assert bench.kernel_roofline("k", nbytes, 3.0, prefix, (6, 25), True)["profile"]["avg_us"] == 3000.0
+    assert bench.kernel_roofline("k", nbytes, 4.0, prefix, (11, 110), True)["profile"]["avg_us"] == 4000.0
+    assert bench.kernel_roofline("k", nbytes, 4.0, prefix, (1, 50), True)["traffic"] is None
